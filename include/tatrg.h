@@ -1,0 +1,129 @@
+/*
+ * tatrg.h - C ABI of the MI355X (gfx950) Triad-ATRG coarse-graining library.
+ *
+ * Method: Sugimoto & Sasaki, "Applying the Triad network representation to four-dimensional
+ * ATRG method", LATTICE2024, arXiv:2412.14104.  One RG step coarse-grains the 4D Ising
+ * tensor network along one direction: canonical form and bond swap of the unit cell
+ * (Section 2, Eq. (1)), oversampled isometries (Eqs. (2)-(3)), triad tensors (Eqs. (4)-(11)),
+ * squeezers (the squeezer cost function of Section 2) and the O(r^2 chi^7) contraction
+ * (Eqs. (makeMG), (makeMH)).  Every randomized SVD uses a Gaussian sketch with q QR
+ * (power) iterations (Table 1).  The partition function is Z = tTr prod T (Section 3).
+ *
+ * Conventions
+ *  - All device pointers are HIP device memory on the device that is current when
+ *    tatrg_create is called; all host pointers are ordinary host memory.
+ *  - Matrices are row-major float64.  The caller owns every buffer passed in, including the
+ *    workspace; the library never allocates device memory after tatrg_create returns.
+ *  - Calls are asynchronous on the stream given to tatrg_create unless documented as
+ *    synchronising.  A handle must not be used from two threads at once.
+ *  - Errors: invalid arguments are reported synchronously (TATRG_EINVAL); HIP launch
+ *    errors as TATRG_EHIP; numerical faults detected on the device (non-finite c_k,
+ *    non-positive Cholesky pivot, non-positive final trace) set a sticky device flag that
+ *    the next synchronising call reports as TATRG_ENUMERIC.  tatrg_last_error returns a
+ *    message for the last failure of a handle.
+ */
+#ifndef TATRG_H
+#define TATRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TATRG_OK = 0,
+  TATRG_EINVAL = -1,   /* invalid configuration or argument                         */
+  TATRG_ENOMEM = -2,   /* workspace smaller than tatrg_workspace_bytes()            */
+  TATRG_EHIP = -3,     /* a HIP runtime call or kernel launch failed                */
+  TATRG_ENUMERIC = -4, /* device-side numerical fault (sticky until tatrg_init_tensor) */
+  TATRG_ESTATE = -5    /* call out of order (e.g. step before init, past n_steps)    */
+} tatrg_status;
+
+typedef enum {
+  TATRG_FP64 = 0,   /* every contraction in float64 on the FP64 MFMA units           */
+  TATRG_BF16X3 = 1  /* contraction GEMMs as three-way split bf16 products with fp32
+                       accumulation; QR, SVD, Cholesky and log-norms stay float64    */
+} tatrg_precision;
+
+typedef struct {
+  int32_t chi;            /* bond dimension chi >= 2                                  */
+  int32_t r;              /* internal-line oversampling r >= 1: L = min(r chi, chi^2)  */
+  int32_t q;              /* QR (power) iterations of every randomized SVD, q >= 0     */
+  int32_t n_steps;        /* RG steps N, 1 <= N <= 64; lattice of 2^N sites            */
+  int32_t batch;          /* number of temperatures; must be 1 in this version         */
+  int32_t precision;      /* tatrg_precision                                          */
+  uint64_t seed;          /* Philox4x32-10 key for every Gaussian sketch               */
+  int32_t record_spectra; /* nonzero: keep per-step singular spectra for readback      */
+  int32_t reserved;
+} tatrg_config;
+
+typedef struct tatrg_handle tatrg_handle;
+
+/* Bytes of device workspace the configuration needs; 0 for an invalid configuration. */
+size_t tatrg_workspace_bytes(const tatrg_config* cfg);
+
+/* Validate cfg, carve the caller's workspace d_ws (>= tatrg_workspace_bytes bytes, 256-byte
+ * aligned) and bind the HIP stream `stream` (a hipStream_t; NULL = default stream).
+ * Returns EINVAL for a bad configuration, ENOMEM for a short workspace.  *out receives the
+ * handle; release it with tatrg_destroy (which does not free d_ws). */
+tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, void* stream,
+                          tatrg_handle** out);
+
+/* Build the initial tensor T = sum_a prod W[a,i] prod W[a,j] from beta (Section 3, the
+ * definitions of T and W; W is the element-wise square root of the printed matrix so that
+ * W W^T is the bond Boltzmann weight) and reset the step counter and log-norm accumulator.
+ * h_betas: host array of `batch` values, each finite and >= 0.  Asynchronous. */
+tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas);
+
+/* One RG step on the device, no host synchronisation: canonical form and normalisation
+ * c_k = |T|_F, bond swap by randomized SVD, isometries, triad tensors, squeezers,
+ * contraction and slot rotation (Section 2).  ESTATE before init or after n_steps steps. */
+tatrg_status tatrg_step(tatrg_handle* h);
+
+/* Standalone randomized SVD A ~= U diag(S) V^T of a device matrix (Introduction, Table 1):
+ * Gaussian sketch of width w drawn from (seed, step = 0, site), q QR iterations, rank k.
+ * d_A: m x n row-major with leading dimension lda >= n (read only).  Outputs (device):
+ * d_U m x k, d_S k, d_Vt k x n (all row-major, dense).  Requires 1 <= k <= w <= min(m, n),
+ * w <= 96.  Uses the handle's workspace, so m*w and n*w must not exceed chi^4 * L of the
+ * handle's configuration.  Asynchronous. */
+tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n, int64_t lda,
+                        int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
+                        double* d_U, double* d_S, double* d_Vt);
+
+/* Synchronising.  h_acc[batch] receives sum_{j<k} 2^-j ln c_j after k steps. */
+tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc);
+
+/* Synchronising; valid after n_steps steps.  Normalises the last tensor once more and traces
+ * it on the 1x1x1x1 periodic lattice:
+ *   ln Z / V = sum_{k=0}^{N} 2^-k ln c_k + 2^-N ln tTr,    f = -(ln Z / V) / beta.
+ * h_f and h_lnzv (host, `batch` entries each; either may be NULL).  f is NaN at beta = 0. */
+tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
+
+/* Synchronising.  Per-step spectra recorded when record_spectra != 0:
+ * which = 0: canonical s (chi), 1: swap sigma (chi), 2/3/4: squeezer S of direction mu = 2/3/4
+ * (chi).  Copies min(cap, chi) values to h_out and the count to *n_out. */
+tatrg_status tatrg_get_spectra(tatrg_handle* h, int32_t step, int32_t which, double* h_out,
+                               int32_t cap, int32_t* n_out);
+
+/* Checkpoint / resume of the RG state (Phi, Psi, step index, log-norm accumulator).
+ * d_phi, d_psi: device buffers of chi^5 doubles each, legs (l1,l2,l3,l4,gamma) row-major with
+ * T = sum_g Phi[..,g] Psi[..,g].  get copies out, set copies in (asynchronous).  set also
+ * clears the sticky numerical flag. */
+tatrg_status tatrg_get_state(tatrg_handle* h, double* d_phi, double* d_psi, int32_t* step,
+                             double* acc);
+tatrg_status tatrg_set_state(tatrg_handle* h, const double* d_phi, const double* d_psi,
+                             int32_t step, double acc);
+
+/* Message describing the last failure on h (never NULL; "" when none). */
+const char* tatrg_last_error(const tatrg_handle* h);
+
+/* Release the handle (not the workspace). */
+void tatrg_destroy(tatrg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TATRG_H */
