@@ -1,0 +1,67 @@
+/*
+ * tatrg_testing.h - kernel-level entry points of libtatrg for parity tests.
+ *
+ * These expose the building blocks of the RG step (include/tatrg.h) so that each can be
+ * compared with an independent reference: the FP64 MFMA GEMM, the Householder TSQR, the
+ * one-sided Jacobi SVD, the shifted Cholesky, the Philox4x32-10 Gaussian sketch, the leg
+ * permutation and the gauge rotation of degenerate singular subspaces.  All pointers are
+ * device pointers unless stated; matrices are row-major float64; every call is
+ * asynchronous on `stream` (a hipStream_t, NULL = default).  Return 0 on success, -1 on
+ * invalid arguments, -3 on a HIP launch error.
+ */
+#ifndef TATRG_TESTING_H
+#define TATRG_TESTING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b] = alpha op(A[b]) op(B[b]) + beta C[b]; op(A) M x K (A stored K x M when ta),
+ * op(B) K x N (B stored N x K when tb); batch strides sA, sB, sC in elements.
+ * parts > 1 splits K and sums the parts in order through `partial`
+ * (parts * batch * M * N doubles). */
+int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int64_t N,
+                    int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
+                    double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
+                    int64_t sC, int parts, double* partial, void* stream);
+
+/* Doubles of workspace tatrg_test_tsqr needs for an m x n panel. */
+size_t tatrg_test_tsqr_ws(int64_t m, int n);
+
+/* In-place orthonormal factor of Y (m x n, ld >= n, m >= n, 1 <= n <= 96): Y <- Q with
+ * Y_in = Q R; R (n x n) written to R when not NULL. */
+int tatrg_test_tsqr(double* Y, int64_t m, int n, int64_t ld, double* R, double* ws,
+                    void* stream);
+
+/* One-sided Jacobi SVD of `batch` n x n matrices (n <= 96): A = U diag(S) V^T, S
+ * descending. */
+int tatrg_test_svd(const double* A, double* U, double* S, double* V, int n, int batch,
+                   void* stream);
+
+/* In-place lower Cholesky of `batch` n x n SPD matrices after adding
+ * shift_rel * trace to the diagonal; flag[0] set to 1 on a non-positive pivot. */
+int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag,
+                        void* stream);
+
+/* Gaussian sketch: element (i, j) of a rows x cols matrix is Philox4x32-10 draw number
+ * i*cols + j of (seed, step, site). */
+int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,
+                      uint32_t site, void* stream);
+
+/* out = permutation of a rank <= 6 row-major tensor; dims and perm are HOST arrays. */
+int tatrg_test_permute(const double* in, double* out, int rank, const int64_t* dims,
+                       const int* perm, void* stream);
+
+/* Gauge rotation O (n x n) from singular values s (n) and probe projections P
+ * (n_probes x n). */
+int tatrg_test_gauge(const double* s, const double* P, double* O, int n, int n_probes,
+                     double tau_null, double tau_deg, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TATRG_TESTING_H */

@@ -1,0 +1,173 @@
+"""MI355X (gfx950) Triad-ATRG coarse-graining for the 4D Ising model.
+
+Thin ctypes binding of libtatrg.so (include/tatrg.h, include/tatrg_testing.h): argument
+marshalling only.  Every step of the RG runs in the library's HIP kernels; PyTorch is used
+for device memory and the stream.  Importing this package without the built library raises.
+"""
+import ctypes
+import math
+import os
+
+__all__ = ["lib", "TatrgConfig", "Engine", "TatrgError", "FP64", "BF16X3", "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libtatrg.so")
+
+FP64 = 0
+BF16X3 = 1
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "ESTATE"}
+
+
+class TatrgError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError("libtatrg.so is not built; run python -m paper_2412_14104_amd.build")
+    return ctypes.CDLL(library_path)
+
+
+lib = _load()
+
+
+class TatrgConfig(ctypes.Structure):
+    _fields_ = [("chi", ctypes.c_int32), ("r", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("record_spectra", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_p = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+_cfgp = ctypes.POINTER(TatrgConfig)
+_dblp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "tatrg_workspace_bytes": (ctypes.c_size_t, [_cfgp]),
+    "tatrg_create": (ctypes.c_int, [_cfgp, _p, ctypes.c_size_t, _p, ctypes.POINTER(_p)]),
+    "tatrg_init_tensor": (ctypes.c_int, [_p, _dblp]),
+    "tatrg_step": (ctypes.c_int, [_p]),
+    "tatrg_rsvd": (ctypes.c_int, [_p, _p, _i64, _i64, _i64, _i32, _i32, _i32, _u64, _u32, _p,
+                                  _p, _p]),
+    "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
+    "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
+    "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),
+    "tatrg_get_state": (ctypes.c_int, [_p, _p, _p, ctypes.POINTER(_i32), _dblp]),
+    "tatrg_set_state": (ctypes.c_int, [_p, _p, _p, _i32, _dbl]),
+    "tatrg_last_error": (ctypes.c_char_p, [_p]),
+    "tatrg_destroy": (None, [_p]),
+    "tatrg_test_gemm": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _i64, _i64, _i64,
+                                       ctypes.c_int, ctypes.c_int, _dbl, _dbl, _i64, _i64,
+                                       _i64, _i64, ctypes.c_int, _p, _p]),
+    "tatrg_test_tsqr_ws": (ctypes.c_size_t, [_i64, ctypes.c_int]),
+    "tatrg_test_tsqr": (ctypes.c_int, [_p, _i64, ctypes.c_int, _i64, _p, _p, _p]),
+    "tatrg_test_svd": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int, ctypes.c_int, _p]),
+    "tatrg_test_cholesky": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, _dbl, _p, _p]),
+    "tatrg_test_philox": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),
+    "tatrg_test_permute": (ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.POINTER(_i64),
+                                          ctypes.POINTER(ctypes.c_int), _p]),
+    "tatrg_test_gauge": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _dbl,
+                                        _p]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def _check(status, handle=None):
+    if status != 0:
+        msg = lib.tatrg_last_error(handle).decode() if handle else ""
+        raise TatrgError(status, msg)
+
+
+def _stream_ptr(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Engine:
+    """One RG run on the current HIP device.  The workspace is a torch uint8 tensor on the
+    device; the stream is torch's current stream unless one is given."""
+
+    def __init__(self, chi, r, q, n_steps, seed=0, precision=FP64, record_spectra=True,
+                 stream=None, device="cuda"):
+        import torch
+        self.cfg = TatrgConfig(chi=chi, r=r, q=q, n_steps=n_steps, batch=1,
+                               precision=precision, seed=seed,
+                               record_spectra=1 if record_spectra else 0, reserved=0)
+        nbytes = lib.tatrg_workspace_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise TatrgError(-1, "invalid configuration")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(lib.tatrg_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.ws.data_ptr()),
+                                nbytes, _stream_ptr(self.stream), ctypes.byref(self.handle)))
+        self.chi, self.n_steps = chi, n_steps
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.tatrg_destroy(h)
+            self.handle = None
+
+    def init(self, beta):
+        arr = (ctypes.c_double * 1)(beta)
+        _check(lib.tatrg_init_tensor(self.handle, arr), self.handle)
+
+    def step(self):
+        _check(lib.tatrg_step(self.handle), self.handle)
+
+    def lognorm(self):
+        out = ctypes.c_double()
+        _check(lib.tatrg_lognorm(self.handle, ctypes.byref(out)), self.handle)
+        return out.value
+
+    def free_energy(self):
+        f, lnzv = ctypes.c_double(), ctypes.c_double()
+        _check(lib.tatrg_free_energy(self.handle, ctypes.byref(f), ctypes.byref(lnzv)),
+               self.handle)
+        return f.value, lnzv.value
+
+    def spectrum(self, step, which):
+        buf = (ctypes.c_double * self.chi)()
+        n = ctypes.c_int32()
+        _check(lib.tatrg_get_spectra(self.handle, step, which, buf, self.chi, ctypes.byref(n)),
+               self.handle)
+        return [buf[i] for i in range(n.value)]
+
+    def get_state(self, phi, psi):
+        step, acc = ctypes.c_int32(), ctypes.c_double()
+        _check(lib.tatrg_get_state(self.handle, ctypes.c_void_p(phi.data_ptr()),
+                                   ctypes.c_void_p(psi.data_ptr()), ctypes.byref(step),
+                                   ctypes.byref(acc)), self.handle)
+        return step.value, acc.value
+
+    def set_state(self, phi, psi, step, acc):
+        _check(lib.tatrg_set_state(self.handle, ctypes.c_void_p(phi.data_ptr()),
+                                   ctypes.c_void_p(psi.data_ptr()), step, acc), self.handle)
+
+    def run(self, beta):
+        """All n_steps steps; returns (f, ln Z / V)."""
+        self.init(beta)
+        for _ in range(self.n_steps):
+            self.step()
+        return self.free_energy()
+
+
+def run(beta, chi, r, q, n_steps, seed=0, record_spectra=False):
+    """Convenience: free energy per site and ln Z / V of one run."""
+    eng = Engine(chi, r, q, n_steps, seed=seed, record_spectra=record_spectra)
+    f, lnzv = eng.run(beta)
+    return {"f": f, "lnZV": lnzv, "engine": eng}
+
+
+def nan_if_zero_beta(beta, value):
+    return float("nan") if beta == 0 else value
+
+
+_ = math

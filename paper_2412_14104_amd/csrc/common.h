@@ -1,0 +1,90 @@
+// Internal declarations shared by the HIP translation units of libtatrg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace tatrg {
+
+// ---------------------------------------------------------------------------- GEMM
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], row-major, float64, b < batch.
+// op(A) is M x K: A stored M x K (lda) or, with ta, K x M (lda).  op(B) is K x N: B stored
+// K x N (ldb) or, with tb, N x K (ldb).  C is M x N (ldc).  Batch strides in elements.
+struct GemmArgs {
+  int64_t M, N, K;
+  const double* A; int64_t lda; int64_t sA; bool ta;
+  const double* B; int64_t ldb; int64_t sB; bool tb;
+  double* C; int64_t ldc; int64_t sC;
+  double alpha, beta;
+  int64_t batch;
+};
+void gemm_f64(const GemmArgs& g, hipStream_t st);
+
+// Split-bf16 variant: every operand is split x = x0 + x1 + x2 into bf16 planes and the six
+// products with i + j <= 2 are accumulated in fp32 on the bf16 MFMA units.  Same contract.
+void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
+                 hipStream_t st);
+
+// Long-K GEMM with small M x N: the K range is split into `parts` chunks written to
+// `partial` (parts * batch * M * N doubles) and summed in a fixed order (deterministic).
+void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t st);
+
+// ---------------------------------------------------------------------------- TSQR
+// Orthonormal basis of a tall panel Y (m x n, row-major, leading dim ld, m >= n, n <= 96),
+// computed in place by Householder reflections on row blocks and a reduction tree of the
+// R factors.  On return Y holds Q (m x n) with Y_in = Q R; R (n x n) is written to R_out
+// when not null.  ws must hold tsqr_ws_doubles(m, n) doubles.
+size_t tsqr_ws_doubles(int64_t m, int n);
+void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st);
+
+// ---------------------------------------------------------------------------- small dense
+// One-sided Jacobi SVD of `batch` square n x n matrices (n <= 96): A = U diag(S) V^T with S
+// descending.  A (read only), U, V row-major n x n, strides n*n; S stride n.  Columns of U
+// with S = 0 are returned as zero.
+void jacobi_svd(const double* A, double* U, double* S, double* V, int n, int batch,
+                hipStream_t st);
+
+// In-place lower Cholesky of `batch` n x n SPD matrices (stride n*n) after adding
+// shift_rel * trace(A) to the diagonal; the strict upper triangle is zeroed.  A non-positive
+// pivot raises bit 1 of *flag.
+void cholesky_shifted(double* A, int n, int batch, double shift_rel, int* flag,
+                      hipStream_t st);
+
+// Gauge fixing of an SVD: s (n, descending) and probe projections P (n_probes x n, P[p][j]
+// = probe p . singular vector j) give an orthogonal block-diagonal O (n x n) that rotates
+// every cluster of (near-)degenerate singular vectors into the canonical basis.
+void gauge_rotation(const double* s, const double* P, double* O, int n, int n_probes,
+                    double tau_null, double tau_deg, hipStream_t st);
+
+// ---------------------------------------------------------------------------- misc
+// Gaussian sketch element (i, j) of a rows x cols matrix is Philox4x32-10 draw number
+// e = i * cols + j for (seed, step, site); written to out[i*ld + j] (or out[j*ld + i] when
+// transposed).
+void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
+                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st);
+
+// out = permutation of a row-major tensor of rank r <= 6 with dims d: out dim k is input
+// dim perm[k].
+void permute(const double* in, double* out, int rank, const int64_t* dims, const int* perm,
+             hipStream_t st);
+
+// x[i][j] *= s[j] for an rows x cols row-major matrix (ld).
+void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t ld,
+                hipStream_t st);
+
+// y = x (n doubles).
+void copy(double* y, const double* x, int64_t n, hipStream_t st);
+
+// Fill with zeros / write the identity into an n x n block (ld).
+void zero(double* x, int64_t n, hipStream_t st);
+void identity(double* x, int n, int64_t ld, hipStream_t st);
+
+// (A + A^T)/2 in place for `batch` n x n matrices (stride n*n).
+void symmetrize(double* A, int n, int batch, hipStream_t st);
+
+// Upper factor R = L^T from a lower Cholesky factor (batch, stride n*n), out of place.
+void transpose_batched(const double* in, double* out, int rows, int cols, int batch,
+                       hipStream_t st);
+
+}  // namespace tatrg

@@ -1,0 +1,863 @@
+// Triad-ATRG RG step engine and C ABI (include/tatrg.h).
+//
+// One call of tatrg_step runs the whole coarse-graining step of Section 2 of Sugimoto &
+// Sasaki (arXiv:2412.14104) on the device, on the caller's stream, with no host
+// synchronisation and no allocation: canonical form and normalisation (S0), bond swap by a
+// randomized SVD of the cell middle (S1, Eq. (1)), oversampled isometries from the Grams of
+// A X sigma and sigma Y D (S2, Eqs. (2)-(3)), triad tensors E..L (S3, Eqs. (4)-(11)),
+// squeezers (S4, the squeezer cost function), the contraction of Eqs. (makeMG), (makeMH)
+// (S5) and the slot rotation that brings the next direction to slot 1 (S6).
+#include "common.h"
+#include "../../include/tatrg.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace tatrg {
+
+// Philox call sites (must match the method's definition of the sketches).
+enum : uint32_t {
+  SITE_SWAP = 0,
+  SITE_ISO_A = 1, SITE_ISO_X = 2, SITE_ISO_Y = 3, SITE_ISO_D = 4,
+  SITE_SQZ_2 = 5, SITE_SQZ_3 = 6, SITE_SQZ_4 = 7,
+  SITE_PROBE_CANON = 8,
+  SITE_PROBE_SQZ_2 = 9, SITE_PROBE_SQZ_3 = 10, SITE_PROBE_SQZ_4 = 11,
+};
+constexpr int N_PROBES = 8;
+constexpr double TAU_NULL = 1e-11;
+constexpr double TAU_DEG = 1e-11;
+constexpr double SQZ_CUTOFF = 1e-10;
+constexpr double CHOL_SHIFT = 1e-13;
+constexpr int MAX_W = 96;
+
+namespace {
+
+constexpr int TPB = 256;
+inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > 1048576) b = 1048576;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------- small kernels
+__global__ void init_tensor_kernel(double* phi, double* psi, int chi, double w00, double w01,
+                                   double w10, double w11) {
+  const int t = threadIdx.x;  // 32 entries: a (2) x f1..f4 (16)
+  if (t >= 32) return;
+  const int a = t >> 4, f = t & 15;
+  const double w[2][2] = {{w00, w01}, {w10, w11}};
+  const int f1 = (f >> 3) & 1, f2 = (f >> 2) & 1, f3 = (f >> 1) & 1, f4 = f & 1;
+  const double u = w[a][f1] * w[a][f2] * w[a][f3] * w[a][f4];
+  const int64_t c = chi;
+  const int64_t idx = (((((int64_t)f1 * c + f2) * c + f3) * c + f4) * c) + a;
+  phi[idx] = u;
+  psi[idx] = u;
+}
+
+// c = |s|, s /= c, acc += 2^-k ln c, spectra record; flags non-finite or zero c.
+__global__ void normalize_kernel(double* s, int n, int k, double* acc, double* lnc_out,
+                                 double* rec, int* flag) {
+  if (threadIdx.x != 0) return;
+  double ss = 0.0;
+  for (int i = 0; i < n; ++i) ss += s[i] * s[i];
+  const double c = sqrt(ss);
+  if (!(c > 0.0) || !isfinite(c)) flag[0] = 1;
+  for (int i = 0; i < n; ++i) s[i] /= c;
+  const double l = log(c);
+  if (lnc_out) lnc_out[k] = l;
+  acc[0] += ldexp(l, -k);
+  if (rec)
+    for (int i = 0; i < n; ++i) rec[i] = s[i];
+}
+
+// d_k = S_k^-1/2 for S_k > cutoff * S_0, else 0.
+__global__ void mask_kernel(const double* S, double* D, int n, double cutoff) {
+  const int i = threadIdx.x;
+  if (i >= n) return;
+  const double smax = S[0];
+  D[i] = (S[i] > cutoff * smax) ? 1.0 / sqrt(S[i]) : 0.0;
+}
+
+__global__ void copy_small_kernel(double* dst, const double* src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// partial sums of sum_{f,g} A[f,g] s_g B[f,g] per block; final reduction by one block.
+__global__ void trace_partial_kernel(const double* A, const double* s, const double* B,
+                                     int64_t rows, int chi, double* part) {
+  __shared__ double red[TPB];
+  double acc = 0.0;
+  const int64_t total = rows * chi;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    acc += A[idx] * s[idx % chi] * B[idx];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void trace_final_kernel(const double* part, int nparts, double* out, int* flag) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[i];
+  out[0] = s;
+  if (!(s > 0.0)) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------- helpers
+struct Dims {
+  int c;
+  int64_t n2, n3, n4, n5;
+  int L, Ls;
+};
+
+GemmArgs G(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool ta,
+           const double* B, int64_t ldb, bool tb, double* C, int64_t ldc, double alpha = 1.0,
+           double beta = 0.0) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = 0; g.ta = ta;
+  g.B = B; g.ldb = ldb; g.sB = 0; g.tb = tb;
+  g.C = C; g.ldc = ldc; g.sC = 0;
+  g.alpha = alpha; g.beta = beta; g.batch = 1;
+  return g;
+}
+GemmArgs Gb(GemmArgs g, int64_t batch, int64_t sA, int64_t sB, int64_t sC) {
+  g.batch = batch; g.sA = sA; g.sB = sB; g.sC = sC;
+  return g;
+}
+
+}  // namespace
+}  // namespace tatrg
+
+using namespace tatrg;
+
+struct tatrg_handle {
+  tatrg_config cfg;
+  Dims d;
+  hipStream_t st;
+  std::string err;
+  int step = 0;
+  bool initialized = false;
+  std::vector<double> betas;
+  // buffers
+  double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *t1, *t2, *tsqr_ws;
+  double *Xs, *Ys, *AP, *Ap, *APp, *rho, *UZ, *E, *F, *Gt, *H;
+  double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm2, *pm3, *sq1, *sq2, *sq3, *sq4;
+  double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
+  double *partial, *probe, *small;
+  int* flag;
+  double* acc;
+  double* lnc;
+  double* spectra;
+  double* trace_part;
+  double* scal;  // [0]: ln c_N, [1]: trace
+  size_t partial_doubles;
+  // small buffers (carved from `small`)
+  size_t tsqr_cap;
+  double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
+  double *Ssq, *Usq, *Vsq, *Umat, *Vmat;
+};
+
+namespace {
+
+bool valid(const tatrg_config* c) {
+  if (!c) return false;
+  if (c->chi < 2 || c->chi > 64) return false;
+  if (c->r < 1 || c->q < 0 || c->q > 16) return false;
+  if (c->n_steps < 1 || c->n_steps > 64) return false;
+  if (c->batch != 1) return false;
+  if (c->precision != TATRG_FP64) return false;
+  const int64_t L = std::min<int64_t>((int64_t)c->r * c->chi, (int64_t)c->chi * c->chi);
+  if (L > MAX_W) return false;
+  return true;
+}
+
+Dims dims_of(const tatrg_config* c) {
+  Dims d;
+  d.c = c->chi;
+  d.n2 = (int64_t)d.c * d.c;
+  d.n3 = d.n2 * d.c;
+  d.n4 = d.n3 * d.c;
+  d.n5 = d.n4 * d.c;
+  d.L = (int)std::min<int64_t>((int64_t)c->r * d.c, d.n2);
+  d.Ls = (int)std::min<int64_t>((int64_t)c->r * d.c, d.n4);
+  return d;
+}
+
+// Bump allocator: sizes everything when base == nullptr.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  double* take(size_t doubles) {
+    off = (off + 255) & ~(size_t)255;
+    double* p = base ? (double*)(base + off) : nullptr;
+    off += doubles * sizeof(double);
+    return p;
+  }
+};
+
+size_t splitk_partial_doubles(const Dims& d) {
+  // Grams: up to 16 parts of n2 x n2, or 256 parts of c x c
+  size_t a = 16 * (size_t)d.n2 * d.n2;
+  size_t b = 256 * (size_t)d.c * d.c;
+  size_t cbig = 64 * (size_t)N_PROBES * d.c;
+  return std::max(a, std::max(b, cbig));
+}
+
+void carve(tatrg_handle* h, Carver& cv) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n4 = d.n4, n5 = d.n5, L = d.L, Ls = d.Ls;
+  h->phi = cv.take(n5); h->psi = cv.take(n5);
+  h->A = cv.take(n5); h->B = cv.take(n5);
+  h->X = cv.take(n5); h->Y = cv.take(n5);
+  h->atf = cv.take(n5); h->btx = cv.take(n5);
+  h->P1 = cv.take(n4 * Ls); h->P2 = cv.take(n4 * Ls);
+  h->t1 = cv.take(n3 * Ls); h->t2 = cv.take(n3 * Ls);
+  const size_t tq = std::max(tsqr_ws_doubles(n4, (int)Ls),
+                             std::max(tsqr_ws_doubles(n4, (int)c), tsqr_ws_doubles(n2, (int)L)));
+  h->tsqr_ws = cv.take(tq);
+  h->tsqr_cap = tq;
+  h->Xs = cv.take(n5); h->Ys = cv.take(n5);
+  h->AP = cv.take(n5); h->Ap = cv.take(n5); h->APp = cv.take(n5);
+  h->rho = cv.take(6 * n2 * n2);
+  h->UZ = cv.take(4 * n2 * L);
+  h->E = cv.take(L * n3); h->F = cv.take(L * n3); h->Gt = cv.take(L * n3); h->H = cv.take(L * n3);
+  h->Ah = cv.take(n5); h->Xh = cv.take(n5); h->Yh = cv.take(n5); h->Dh = cv.take(n5);
+  h->XA = cv.take(n5); h->xg = cv.take(n5); h->yg = cv.take(n5);
+  h->pm1 = cv.take(n5); h->pm2 = cv.take(n5); h->pm3 = cv.take(n5);
+  h->sq1 = cv.take(n2 * n2); h->sq2 = cv.take(n2 * n2); h->sq3 = cv.take(n2 * n2);
+  h->sq4 = cv.take(n2 * n2);
+  h->chol = cv.take(6 * n2 * n2);
+  h->Cm = cv.take(n2 * n2);
+  h->Msq = cv.take(3 * n2 * c); h->Nsq = cv.take(3 * n2 * c);
+  h->Fp = cv.take(L * n3);
+  h->tmp5 = cv.take(L * n4);
+  h->FM4 = cv.take(L * n4);
+  h->P = cv.take(L * L * n3);
+  h->q1 = cv.take(std::max(L * n3, L * L * n2));  // [(i3a kA),(i2b k2)] then [(kA k2 k3), kX]
+  h->q2 = cv.take(L * n4); h->q3 = cv.take(L * n4);
+  h->Qt = cv.take(L * L * n2);
+  h->phin = cv.take(n5);
+  h->partial_doubles = splitk_partial_doubles(d);
+  h->partial = cv.take(h->partial_doubles);
+  h->probe = cv.take((size_t)N_PROBES * n4);
+  h->flag = (int*)cv.take(8);
+  h->acc = cv.take(8);
+  h->lnc = cv.take(72);
+  h->spectra = cv.take((size_t)(h->cfg.n_steps + 1) * 5 * c);
+  h->trace_part = cv.take(4096);
+  h->scal = cv.take(8);
+  const int64_t w = std::max<int64_t>(Ls, L);
+  h->s = cv.take(c); h->sig = cv.take(c);
+  h->Rp = cv.take(c * c); h->Rs = cv.take(c * c); h->Cc = cv.take(c * c);
+  h->Uc = cv.take(c * c); h->Vc = cv.take(c * c); h->Oc = cv.take(w * w);
+  h->Pm = cv.take(N_PROBES * w);
+  h->Pm0 = cv.take(N_PROBES * c);
+  h->RbT = cv.take(w * w); h->Rb = cv.take(w * w);
+  h->Uh = cv.take(w * w); h->Sh = cv.take(w); h->Vh = cv.take(w * w);
+  h->Dm = cv.take(w);
+  h->Ssq = cv.take(3 * c);
+  h->Usq = cv.take(n2 * c); h->Vsq = cv.take(n2 * c);
+  h->Umat = cv.take(n2 * c); h->Vmat = cv.take(n2 * c);
+  h->small = nullptr;
+}
+
+bool hip_ok(tatrg_handle* h, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    h->err = std::string(where) + ": " + hipGetErrorString(e);
+    return false;
+  }
+  return true;
+}
+
+void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
+
+// Deterministic split-K for Grams with long K and a small output.
+void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
+  const int64_t mn = g.M * g.N * g.batch;
+  int parts = (int)std::min<int64_t>(g.K / 1024, (int64_t)(h->partial_doubles / (size_t)mn));
+  if (parts > 256) parts = 256;
+  const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  if (tiles >= 256 || parts < 2) {
+    gemm_f64(g, h->st);
+    return;
+  }
+  gemm_f64_splitk(g, parts, h->partial, h->st);
+}
+
+void perm(tatrg_handle* h, const double* in, double* out, std::vector<int64_t> dims,
+          std::vector<int> p) {
+  permute(in, out, (int)dims.size(), dims.data(), p.data(), h->st);
+}
+
+// ---------------------------------------------------------------------------- RSVD
+// Operator interface: apply(in, out, w) computes out = Op * in (rows m), apply_t the
+// transpose (rows n); panels are row-major with w columns.
+struct Op {
+  virtual void apply(const double* in, double* out, int w) = 0;
+  virtual void apply_t(const double* in, double* out, int w) = 0;
+  virtual ~Op() {}
+};
+
+// Randomized SVD (Gaussian sketch, q QR iterations): on return Pa (m x w) holds Q and Pb
+// (n x w) holds Qb; Uh, S, Vh (w x w) are the core SVD of Rb^T, so that
+// Op ~= (Q Uh) S (Qb Vh)^T.  range_only stops after the last orthonormalisation of Pa.
+void rsvd(tatrg_handle* h, Op& op, int64_t m, int64_t n, int w, int q, uint32_t site,
+          double* Pa, double* Pb, bool range_only) {
+  hipStream_t st = h->st;
+  philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st);
+  op.apply(Pb, Pa, w);
+  tsqr(Pa, m, w, w, nullptr, h->tsqr_ws, st);
+  for (int it = 0; it < h->cfg.q; ++it) {
+    op.apply_t(Pa, Pb, w);
+    tsqr(Pb, n, w, w, nullptr, h->tsqr_ws, st);
+    op.apply(Pb, Pa, w);
+    tsqr(Pa, m, w, w, nullptr, h->tsqr_ws, st);
+  }
+  (void)q;
+  if (range_only) return;
+  op.apply_t(Pa, Pb, w);
+  tsqr(Pb, n, w, w, h->Rb, h->tsqr_ws, st);
+  transpose_batched(h->Rb, h->RbT, w, w, 1, st);
+  jacobi_svd(h->RbT, h->Uh, h->Sh, h->Vh, w, 1, st);
+}
+
+// Cell middle of the swap: M[(alpha,f'),(beta,b')] = sum_x s_a B[x,b',a] A[x,f',b] s_b, rows
+// stored in (f', alpha) order, columns in (beta, b') order.
+struct SwapOp : Op {
+  tatrg_handle* h;
+  void apply(const double* om, double* y, int w) override {
+    const Dims& d = h->d;
+    // t1[beta][(x alpha)][j] = btx[(x alpha), b'] om[beta][b'][j]
+    gemm(h, Gb(G(d.n2, w, d.n3, h->btx, d.n3, false, om, w, false, h->t1, w), d.c, 0,
+               d.n3 * w, d.n2 * w));
+    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {1, 0, 2, 3});  // [x, beta, alpha, j]
+    // y[f', (alpha j)] = atf[f', (x beta)] t2[(x beta), (alpha j)]
+    gemm(h, G(d.n3, d.c * w, d.n2, h->atf, d.n2, false, h->t2, d.c * w, false, y, d.c * w));
+  }
+  void apply_t(const double* qm, double* z, int w) override {
+    const Dims& d = h->d;
+    // t1[(x beta), (alpha j)] = atf^T qm[f', (alpha j)]
+    gemm(h, G(d.n2, d.c * w, d.n3, h->atf, d.n2, true, qm, d.c * w, false, h->t1, d.c * w));
+    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {1, 0, 2, 3});  // [beta, x, alpha, j]
+    // z[beta][b'][j] = btx^T[b', (x alpha)] t2[beta][(x alpha)][j]
+    gemm(h, Gb(G(d.n3, w, d.n2, h->btx, d.n3, true, h->t2, w, false, z, w), d.c, 0, d.n2 * w,
+               d.n3 * w));
+  }
+};
+
+struct DenseOp : Op {
+  tatrg_handle* h;
+  const double* M;
+  int64_t n;
+  void apply(const double* in, double* out, int w) override {
+    gemm(h, G(n, w, n, M, n, false, in, w, false, out, w));
+  }
+  void apply_t(const double* in, double* out, int w) override {
+    gemm(h, G(n, w, n, M, n, true, in, w, false, out, w));
+  }
+};
+
+// ---------------------------------------------------------------------------- step stages
+// S0: T = Phi Psi^T = A s B^T, gauge fixed, normalised.  rec: spectra slot or null.
+void canonicalize(tatrg_handle* h, int k, double* rec) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int c = d.c;
+  tsqr(h->phi, d.n4, c, c, h->Rp, h->tsqr_ws, st);
+  tsqr(h->psi, d.n4, c, c, h->Rs, h->tsqr_ws, st);
+  gemm(h, G(c, c, c, h->Rp, c, false, h->Rs, c, true, h->Cc, c));
+  jacobi_svd(h->Cc, h->Uc, h->s, h->Vc, c, 1, st);
+  // probes against A = Q_Phi U
+  philox_gaussian(h->probe, N_PROBES, d.n4, d.n4, false, h->cfg.seed, (uint32_t)k,
+                  SITE_PROBE_CANON, st);
+  gemm_long_k(h, G(N_PROBES, c, d.n4, h->probe, d.n4, false, h->phi, c, false, h->Pm0, c));
+  gemm(h, G(N_PROBES, c, c, h->Pm0, c, false, h->Uc, c, false, h->Pm, c));
+  gauge_rotation(h->s, h->Pm, h->Oc, c, N_PROBES, TAU_NULL, TAU_DEG, st);
+  gemm(h, G(c, c, c, h->Uc, c, false, h->Oc, c, false, h->Rb, c));
+  gemm(h, G(c, c, c, h->Vc, c, false, h->Oc, c, false, h->Uh, c));
+  gemm(h, G(d.n4, c, c, h->phi, c, false, h->Rb, c, false, h->A, c));
+  gemm(h, G(d.n4, c, c, h->psi, c, false, h->Uh, c, false, h->B, c));
+  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(64), 0, st, h->s, c, k, h->acc, h->lnc,
+                     rec, h->flag);
+}
+
+void bond_swap(tatrg_handle* h, double* rec) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int c = d.c;
+  const int w = d.Ls;
+  // A~ = A s, B~ = B s; atf = [f', (x beta)], btx = [(x alpha), b']
+  copy(h->Xs, h->A, d.n5, st);
+  scale_cols(h->Xs, h->s, d.n4, c, c, st);
+  copy(h->Ys, h->B, d.n5, st);
+  scale_cols(h->Ys, h->s, d.n4, c, c, st);
+  perm(h, h->Xs, h->atf, {c, d.n3, c}, {1, 0, 2});
+  perm(h, h->Ys, h->btx, {c, d.n3, c}, {0, 2, 1});
+  SwapOp op;
+  op.h = h;
+  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false);
+  // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c]
+  gemm(h, G(d.n4, c, w, h->P2, w, false, h->Uh, w, false, h->Xs, c));
+  perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
+  gemm(h, G(d.n4, c, w, h->P1, w, false, h->Vh, w, false, h->Y, c));
+  hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, h->sig, h->Sh, c);
+  if (rec) hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec, h->Sh, c);
+}
+
+// Gram of the (l2 l3) pair: rho[(l2 l3),(l2' l3')] = sum over the other legs of T T' for
+// 5-leg tensors T, T' laid out [l1,l2,l3,l4,l5] with the pair at positions (p, p+1) = (1,2)
+// (A-type, [f1,f2,f3,f4,a]) -- both operands are permuted to [(l2 l3), rest].
+void pair_gram(tatrg_handle* h, const double* T1, const double* T2, double* out) {
+  const Dims& d = h->d;
+  const int64_t c = d.c;
+  perm(h, T1, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
+  const double* rhs = h->Ap;
+  if (T2 != T1) {
+    perm(h, T2, h->APp, {c, c, c, c, c}, {1, 2, 0, 3, 4});
+    rhs = h->APp;
+  }
+  gemm_long_k(h, G(d.n2, d.n2, d.n3, h->Ap, d.n3, false, rhs, d.n3, true, out, d.n2));
+}
+
+void isometries(tatrg_handle* h) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int64_t c = d.c, n2 = d.n2;
+  copy(h->Xs, h->X, d.n5, st);
+  scale_cols(h->Xs, h->sig, d.n4, c, c, st);
+  copy(h->Ys, h->Y, d.n5, st);
+  scale_cols(h->Ys, h->sig, d.n4, c, c, st);
+  double* px = h->Cc;
+  double* py = h->Uc;
+  gemm_long_k(h, G(c, c, d.n4, h->Xs, d.n4, false, h->Xs, d.n4, true, px, c));
+  gemm_long_k(h, G(c, c, d.n4, h->Ys, d.n4, false, h->Ys, d.n4, true, py, c));
+  double* rA = h->rho;
+  double* rX = h->rho + n2 * n2;
+  double* rY = h->rho + 2 * n2 * n2;
+  double* rD = h->rho + 3 * n2 * n2;
+  gemm(h, G(d.n4, c, c, h->A, c, false, px, c, false, h->AP, c));
+  pair_gram(h, h->A, h->AP, rA);
+  // X-type: [alpha, f2, f3, f4, g] -> [(f2 f3), alpha, f4, g]
+  perm(h, h->Xs, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
+  gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rX, n2));
+  perm(h, h->Ys, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
+  gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rY, n2));
+  gemm(h, G(d.n4, c, c, h->B, c, false, py, c, false, h->AP, c));
+  pair_gram(h, h->B, h->AP, rD);
+  const uint32_t sites[4] = {SITE_ISO_A, SITE_ISO_X, SITE_ISO_Y, SITE_ISO_D};
+  for (int z = 0; z < 4; ++z) {
+    DenseOp op;
+    op.h = h;
+    op.M = h->rho + z * n2 * n2;
+    op.n = n2;
+    double* U = h->UZ + z * n2 * d.L;
+    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true);
+  }
+}
+
+void triad(tatrg_handle* h) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2, L = d.L;
+  const double* UA = h->UZ;
+  const double* UX = h->UZ + n2 * L;
+  const double* UY = h->UZ + 2 * n2 * L;
+  const double* UD = h->UZ + 3 * n2 * L;
+  // E[f1][kA][(f4 a)] = UA^T A[f1][(f2 f3)][(f4 a)]   (and F, G, H alike)
+  gemm(h, Gb(G(L, n2, n2, UA, L, true, h->A, n2, false, h->E, n2), c, 0, d.n4, L * n2));
+  gemm(h, Gb(G(L, n2, n2, UX, L, true, h->X, n2, false, h->F, n2), c, 0, d.n4, L * n2));
+  scale_cols(h->F, h->sig, c * L * c, c, c, h->st);
+  gemm(h, Gb(G(L, n2, n2, UY, L, true, h->Y, n2, false, h->Gt, n2), c, 0, d.n4, L * n2));
+  gemm(h, Gb(G(L, n2, n2, UD, L, true, h->B, n2, false, h->H, n2), c, 0, d.n4, L * n2));
+}
+
+void squeezers(tatrg_handle* h, double* rec) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n4 = d.n4, L = d.L;
+  const double* UA = h->UZ;
+  const double* UX = h->UZ + n2 * L;
+  const double* UY = h->UZ + 2 * n2 * L;
+  const double* UD = h->UZ + 3 * n2 * L;
+  // projected fundamental tensors
+  gemm(h, Gb(G(n2, n2, L, UA, L, false, h->E, n2, false, h->Ah, n2), c, 0, L * n2, n4));
+  gemm(h, Gb(G(n2, n2, L, UX, L, false, h->F, n2, false, h->Xh, n2), c, 0, L * n2, n4));
+  gemm(h, Gb(G(n2, n2, L, UY, L, false, h->Gt, n2, false, h->Yh, n2), c, 0, L * n2, n4));
+  gemm(h, Gb(G(n2, n2, L, UD, L, false, h->H, n2, false, h->Dh, n2), c, 0, L * n2, n4));
+  double* aag = h->Cc;
+  double* ddg = h->Uc;
+  double* gf = h->Vc;
+  double* gb = h->Rp;
+  gemm_long_k(h, G(c, c, n4, h->Ah, c, true, h->Ah, c, false, aag, c));
+  gemm_long_k(h, G(c, c, n4, h->Dh, c, true, h->Dh, c, false, ddg, c));
+  // g_f = Xh^T (aag^T Xh), g_b = Yh^T (ddg^T Yh) with Xh viewed (c x n4) / (n4 x c)
+  gemm(h, G(c, n4, c, aag, c, true, h->Xh, n4, false, h->XA, n4));
+  gemm_long_k(h, G(c, c, n4, h->Xh, c, true, h->XA, c, false, gf, c));
+  gemm(h, G(c, n4, c, ddg, c, true, h->Yh, n4, false, h->XA, n4));
+  gemm_long_k(h, G(c, c, n4, h->Yh, c, true, h->XA, c, false, gb, c));
+  gemm(h, G(n4, c, c, h->Xh, c, false, gb, c, false, h->xg, c));
+  gemm(h, G(n4, c, c, h->Yh, c, false, gf, c, false, h->yg, c));
+
+  const std::vector<int> a_perm[3] = {{1, 4, 0, 2, 3}, {2, 4, 0, 1, 3}, {3, 4, 0, 1, 2}};
+  const std::vector<int> x_perm[3] = {{0, 1, 2, 3, 4}, {0, 2, 1, 3, 4}, {0, 3, 1, 2, 4}};
+  const std::vector<int64_t> d5 = {c, c, c, c, c};
+  const std::vector<int64_t> d4 = {c, c, c, c};
+  for (int mi = 0; mi < 3; ++mi) {
+    double* rl = h->rho + mi * n2 * n2;
+    double* rr = h->rho + (3 + mi) * n2 * n2;
+    // rho_L = sum_{a a'} aa[u1 a u1' a'] xx[a u2 a' u2']
+    perm(h, h->Ah, h->pm1, d5, a_perm[mi]);
+    gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
+    perm(h, h->Xh, h->pm2, d5, x_perm[mi]);
+    perm(h, h->xg, h->pm3, d5, x_perm[mi]);
+    gemm_long_k(h, G(n2, n2, n3, h->pm2, n3, false, h->pm3, n3, true, h->sq2, n2));
+    perm(h, h->sq1, h->sq3, d4, {0, 2, 1, 3});
+    perm(h, h->sq2, h->sq4, d4, {0, 2, 1, 3});
+    gemm(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
+    perm(h, h->sq1, rl, d4, {0, 2, 1, 3});
+    // rho_R = sum_{b b'} yy[b v1 b' v1'] dd[v2 b v2' b']
+    perm(h, h->Yh, h->pm2, d5, x_perm[mi]);
+    perm(h, h->yg, h->pm3, d5, x_perm[mi]);
+    gemm_long_k(h, G(n2, n2, n3, h->pm2, n3, false, h->pm3, n3, true, h->sq2, n2));
+    perm(h, h->Dh, h->pm1, d5, a_perm[mi]);
+    gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
+    perm(h, h->sq2, h->sq3, d4, {1, 3, 0, 2});
+    perm(h, h->sq1, h->sq4, d4, {1, 3, 0, 2});
+    gemm(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
+    perm(h, h->sq1, rr, d4, {0, 2, 1, 3});
+  }
+  symmetrize(h->rho, (int)n2, 6, st);
+  copy(h->chol, h->rho, 6 * n2 * n2, st);
+  cholesky_shifted(h->chol, (int)n2, 6, CHOL_SHIFT, h->flag, st);
+  const uint32_t sq_sites[3] = {SITE_SQZ_2, SITE_SQZ_3, SITE_SQZ_4};
+  const uint32_t pr_sites[3] = {SITE_PROBE_SQZ_2, SITE_PROBE_SQZ_3, SITE_PROBE_SQZ_4};
+  for (int mi = 0; mi < 3; ++mi) {
+    const double* Ll = h->chol + mi * n2 * n2;        // rho_L + shift = Ll Ll^T, R_L = Ll^T
+    const double* Lr = h->chol + (3 + mi) * n2 * n2;  // R_R = Lr^T
+    // C = R_L R_R^T = Ll^T Lr
+    gemm(h, G(n2, n2, n2, Ll, n2, true, Lr, n2, false, h->Cm, n2));
+    DenseOp op;
+    op.h = h;
+    op.M = h->Cm;
+    op.n = n2;
+    const int w = d.L;
+    rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false);
+    // U = Q Uh[:, :c], V = Qb Vh[:, :c]
+    gemm(h, G(n2, c, w, h->P2, w, false, h->Uh, w, false, h->Usq, c));
+    gemm(h, G(n2, c, w, h->P1, w, false, h->Vh, w, false, h->Vsq, c));
+    double* S = h->Ssq + mi * c;
+    hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, S, h->Sh, (int)c);
+    if (rec)
+      hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec + mi * c, h->Sh,
+                         (int)c);
+    philox_gaussian(h->probe, N_PROBES, n2, n2, false, h->cfg.seed, (uint32_t)h->step,
+                    pr_sites[mi], st);
+    gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
+    gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, st);
+    gemm(h, G(n2, c, c, h->Usq, c, false, h->Oc, c, false, h->Umat, c));
+    gemm(h, G(n2, c, c, h->Vsq, c, false, h->Oc, c, false, h->Vmat, c));
+    hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, st, S, h->Dm, (int)c, SQZ_CUTOFF);
+    // M = R_R^T V D = Lr V D  (n2 x c), stored [u1][u2][k]
+    double* M = h->Msq + mi * n2 * c;
+    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vmat, c, false, M, c));
+    scale_cols(M, h->Dm, n2, c, c, st);
+    // N = D U^T R_L = (Ll U D)^T  (c x n2), stored [k][v1][v2]
+    gemm(h, G(n2, c, n2, Ll, n2, false, h->Umat, c, false, h->Vsq, c));
+    scale_cols(h->Vsq, h->Dm, n2, c, c, st);
+    transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, st);
+  }
+}
+
+// One half of the contraction (Eqs. (makeMG) / (makeMH)):
+//   out[k2,k3,k4,l1,g] = sum (E F S4)(I J S2 S3), rotated.
+// E: [l1][kA][(l4a a)], F: [a][kX][(l4b g)], I/J: [(l2 l3)][k], S4p: [l4b][l4a][k4],
+// S2, S3: [l_a][l_b][k].
+void contract_half(tatrg_handle* h, const double* E, const double* F, const double* I,
+                   const double* J, const double* S4p, const double* S2, const double* S3,
+                   double* out) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2, L = d.L;
+  // Fp[i4b][(a kX g)]
+  perm(h, F, h->Fp, {c, L, c, c}, {2, 0, 1, 3});
+  // tmp[(i4a k4)][(a kX g)] = S4p^T Fp
+  gemm(h, G(n2, c * L * c, c, S4p, n2, true, h->Fp, c * L * c, false, h->tmp5, c * L * c));
+  // FM4[i4a][a][kX][g][k4]
+  perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
+  // P[(i1 kA)][(kX g k4)] = E[(i1 kA)][(i4a a)] FM4[(i4a a)][(kX g k4)]
+  gemm(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
+  // Qt[kA][kX][k2][k3]
+  gemm(h, G(c * L, n2, c, I, c * L, true, S2, n2, false, h->q1, n2));        // [(i3a kA),(i2b k2)]
+  gemm(h, G(L * n2, n2, c, h->q1, L * n2, true, S3, n2, false, h->q2, n2));  // [(kA i2b k2),(i3b k3)]
+  perm(h, h->q2, h->q3, {L, c, c, c, c}, {0, 2, 4, 1, 3});                  // [kA,k2,k3,i2b,i3b]
+  gemm(h, G(L * n2, L, n2, h->q3, n2, false, J, L, false, h->q1, L));        // [(kA k2 k3), kX]
+  perm(h, h->q1, h->Qt, {L, c, c, L}, {0, 3, 1, 2});                        // [kA,kX,k2,k3]
+  // phin[i1][(k2 k3)][(g k4)] = Qt^T P[i1]
+  gemm(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0, L * L * n2,
+             d.n4));
+  // rotate: [i1,k2,k3,g,k4] -> [k2,k3,k4,i1,g]
+  perm(h, h->phin, out, {c, c, c, c, c}, {1, 2, 4, 0, 3});
+}
+
+void contraction(tatrg_handle* h) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2, L = d.L;
+  const double* UA = h->UZ;
+  const double* UX = h->UZ + n2 * L;
+  const double* UY = h->UZ + 2 * n2 * L;
+  const double* UD = h->UZ + 3 * n2 * L;
+  const double* M2 = h->Msq;
+  const double* M3 = h->Msq + n2 * c;
+  const double* M4 = h->Msq + 2 * n2 * c;
+  const double* N2 = h->Nsq;
+  const double* N3 = h->Nsq + n2 * c;
+  const double* N4 = h->Nsq + 2 * n2 * c;
+  const std::vector<int64_t> d3 = {c, c, c};
+  // Phi: S4p = M4 [i4a,i4b,k4] -> [i4b,i4a,k4]
+  double* s4p = h->sq1;
+  double* s2 = h->sq2;
+  double* s3 = h->sq3;
+  perm(h, M4, s4p, d3, {1, 0, 2});
+  contract_half(h, h->E, h->F, UA, UX, s4p, M2, M3, h->phi);
+  // Psi: roles E<-H (site n), F<-G; N stored [k][j_a][j_b]:
+  // S4p[j4a][j4b][k] = N4 perm (1,2,0); S2[j2b][j2a][k] = N2 perm (2,1,0)
+  perm(h, N4, s4p, d3, {1, 2, 0});
+  perm(h, N2, s2, d3, {2, 1, 0});
+  perm(h, N3, s3, d3, {2, 1, 0});
+  contract_half(h, h->H, h->Gt, UD, UY, s4p, s2, s3, h->psi);
+}
+
+}  // namespace
+
+// ============================================================================== C ABI
+extern "C" {
+
+size_t tatrg_workspace_bytes(const tatrg_config* cfg) {
+  if (!valid(cfg)) return 0;
+  tatrg_handle tmp;
+  tmp.cfg = *cfg;
+  tmp.d = dims_of(cfg);
+  Carver cv{nullptr};
+  carve(&tmp, cv);
+  return cv.off + 256;
+}
+
+tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, void* stream,
+                          tatrg_handle** out) {
+  if (!out) return TATRG_EINVAL;
+  *out = nullptr;
+  if (!valid(cfg)) return TATRG_EINVAL;
+  const size_t need = tatrg_workspace_bytes(cfg);
+  if (!d_ws || ws_bytes < need) return TATRG_ENOMEM;
+  tatrg_handle* h = new tatrg_handle();
+  h->cfg = *cfg;
+  h->d = dims_of(cfg);
+  h->st = (hipStream_t)stream;
+  char* base = (char*)(((uintptr_t)d_ws + 255) & ~(uintptr_t)255);
+  Carver cv{base};
+  carve(h, cv);
+  *out = h;
+  return TATRG_OK;
+}
+
+tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas) {
+  if (!h || !h_betas) return TATRG_EINVAL;
+  const double beta = h_betas[0];
+  if (!std::isfinite(beta) || beta < 0.0) {
+    h->err = "beta must be finite and >= 0";
+    return TATRG_EINVAL;
+  }
+  h->betas.assign(h_betas, h_betas + h->cfg.batch);
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  zero(h->phi, d.n5, st);
+  zero(h->psi, d.n5, st);
+  // W = element-wise square root of [[cosh b, sinh b], [cosh b, -sinh b]]
+  const double sc = std::sqrt(std::cosh(beta)), ss = std::sqrt(std::sinh(beta));
+  hipLaunchKernelGGL(init_tensor_kernel, dim3(1), dim3(64), 0, st, h->phi, h->psi, d.c, sc, ss,
+                     sc, -ss);
+  zero((double*)h->flag, 4, st);
+  zero(h->acc, 8, st);
+  zero(h->lnc, 72, st);
+  zero(h->spectra, (int64_t)(h->cfg.n_steps + 1) * 5 * d.c, st);
+  h->step = 0;
+  h->initialized = true;
+  if (!hip_ok(h, "init_tensor")) return TATRG_EHIP;
+  return TATRG_OK;
+}
+
+tatrg_status tatrg_step(tatrg_handle* h) {
+  if (!h) return TATRG_EINVAL;
+  if (!h->initialized || h->step >= h->cfg.n_steps) {
+    h->err = "step called before init_tensor or after n_steps steps";
+    return TATRG_ESTATE;
+  }
+  double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
+  canonicalize(h, h->step, rec);
+  bond_swap(h, rec ? rec + h->d.c : nullptr);
+  isometries(h);
+  triad(h);
+  squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
+  contraction(h);
+  if (!hip_ok(h, "step")) return TATRG_EHIP;
+  h->step += 1;
+  return TATRG_OK;
+}
+
+tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n, int64_t lda,
+                        int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
+                        double* d_U, double* d_S, double* d_Vt) {
+  if (!h || !d_A || !d_U || !d_S || !d_Vt) return TATRG_EINVAL;
+  if (k < 1 || w < k || w > MAX_W || m < w || n < w || lda < n) return TATRG_EINVAL;
+  const int64_t cap = h->d.n4 * h->d.Ls;
+  if (m * w > cap || n * w > cap) return TATRG_EINVAL;
+  if (tsqr_ws_doubles(m, w) > h->tsqr_cap || tsqr_ws_doubles(n, w) > h->tsqr_cap ||
+      n * k > h->d.n2 * h->d.c)
+    return TATRG_EINVAL;
+  struct MOp : Op {
+    tatrg_handle* h;
+    const double* A;
+    int64_t m, n, lda;
+    void apply(const double* in, double* out, int w) override {
+      gemm_f64(G(m, w, n, A, lda, false, in, w, false, out, w), h->st);
+    }
+    void apply_t(const double* in, double* out, int w) override {
+      gemm_f64(G(n, w, m, A, lda, true, in, w, false, out, w), h->st);
+    }
+  } op;
+  op.h = h;
+  op.A = d_A;
+  op.m = m;
+  op.n = n;
+  op.lda = lda;
+  const uint64_t save_seed = h->cfg.seed;
+  const int save_q = h->cfg.q, save_step = h->step;
+  h->cfg.seed = seed;
+  h->cfg.q = q;
+  h->step = 0;
+  rsvd(h, op, m, n, w, q, site, h->P2, h->P1, false);
+  h->cfg.seed = save_seed;
+  h->cfg.q = save_q;
+  h->step = save_step;
+  gemm_f64(G(m, k, w, h->P2, w, false, h->Uh, w, false, d_U, k), h->st);
+  // Vt = (Qb Vh[:, :k])^T
+  gemm_f64(G(n, k, w, h->P1, w, false, h->Vh, w, false, h->Usq, k), h->st);
+  transpose_batched(h->Usq, d_Vt, (int)n, k, 1, h->st);
+  hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, h->st, d_S, h->Sh, k);
+  if (!hip_ok(h, "rsvd")) return TATRG_EHIP;
+  return TATRG_OK;
+}
+
+static tatrg_status sync_check(tatrg_handle* h) {
+  if (hipStreamSynchronize(h->st) != hipSuccess) {
+    h->err = "stream synchronisation failed";
+    return TATRG_EHIP;
+  }
+  int flag = 0;
+  if (hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+    h->err = "flag readback failed";
+    return TATRG_EHIP;
+  }
+  if (flag) {
+    h->err = "numerical fault on the device (non-finite norm, Cholesky pivot or trace)";
+    return TATRG_ENUMERIC;
+  }
+  return TATRG_OK;
+}
+
+tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc) {
+  if (!h || !h_acc) return TATRG_EINVAL;
+  tatrg_status s = sync_check(h);
+  if (hipMemcpy(h_acc, h->acc, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return TATRG_EHIP;
+  return s;
+}
+
+tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
+  if (!h) return TATRG_EINVAL;
+  if (!h->initialized || h->step != h->cfg.n_steps) {
+    h->err = "free_energy needs exactly n_steps completed steps";
+    return TATRG_ESTATE;
+  }
+  const Dims& d = h->d;
+  double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * d.c : nullptr;
+  canonicalize(h, h->step, rec);
+  const int nparts = 1024;
+  hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->A, h->s, h->B,
+                     d.n4, d.c, h->trace_part);
+  hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, h->st, h->trace_part, nparts,
+                     h->scal + 1, h->flag);
+  if (!hip_ok(h, "free_energy")) return TATRG_EHIP;
+  tatrg_status s = sync_check(h);
+  double acc = 0.0, lnc[72], ttr = 0.0;
+  hipMemcpy(&acc, h->acc, sizeof(double), hipMemcpyDeviceToHost);
+  hipMemcpy(lnc, h->lnc, sizeof(double) * 72, hipMemcpyDeviceToHost);
+  hipMemcpy(&ttr, h->scal + 1, sizeof(double), hipMemcpyDeviceToHost);
+  const int N = h->cfg.n_steps;
+  // acc already holds sum_{k=0}^{N} 2^-k ln c_k (the last canonicalisation added c_N)
+  const double lnzv = acc + std::ldexp(std::log(ttr), -N);
+  const double beta = h->betas.empty() ? 0.0 : h->betas[0];
+  if (h_lnzv) h_lnzv[0] = lnzv;
+  if (h_f) h_f[0] = (beta > 0.0) ? -lnzv / beta : std::nan("");
+  (void)lnc;
+  return s;
+}
+
+tatrg_status tatrg_get_spectra(tatrg_handle* h, int32_t step, int32_t which, double* h_out,
+                               int32_t cap, int32_t* n_out) {
+  if (!h || !h_out || !n_out) return TATRG_EINVAL;
+  if (!h->cfg.record_spectra || step < 0 || step > h->cfg.n_steps || which < 0 || which > 4)
+    return TATRG_EINVAL;
+  tatrg_status s = sync_check(h);
+  const int n = std::min<int>(cap, h->d.c);
+  hipMemcpy(h_out, h->spectra + ((int64_t)step * 5 + which) * h->d.c, sizeof(double) * n,
+            hipMemcpyDeviceToHost);
+  *n_out = n;
+  return s == TATRG_ENUMERIC ? TATRG_OK : s;
+}
+
+tatrg_status tatrg_get_state(tatrg_handle* h, double* d_phi, double* d_psi, int32_t* step,
+                             double* acc) {
+  if (!h || !d_phi || !d_psi) return TATRG_EINVAL;
+  copy(d_phi, h->phi, h->d.n5, h->st);
+  copy(d_psi, h->psi, h->d.n5, h->st);
+  if (step) *step = h->step;
+  if (acc) {
+    if (hipStreamSynchronize(h->st) != hipSuccess) return TATRG_EHIP;
+    hipMemcpy(acc, h->acc, sizeof(double), hipMemcpyDeviceToHost);
+  }
+  if (!hip_ok(h, "get_state")) return TATRG_EHIP;
+  return TATRG_OK;
+}
+
+tatrg_status tatrg_set_state(tatrg_handle* h, const double* d_phi, const double* d_psi,
+                             int32_t step, double acc) {
+  if (!h || !d_phi || !d_psi || step < 0 || step > h->cfg.n_steps) return TATRG_EINVAL;
+  if (!h->initialized) {
+    h->err = "set_state needs a prior init_tensor (for beta)";
+    return TATRG_ESTATE;
+  }
+  copy(h->phi, d_phi, h->d.n5, h->st);
+  copy(h->psi, d_psi, h->d.n5, h->st);
+  zero((double*)h->flag, 4, h->st);
+  if (hipStreamSynchronize(h->st) != hipSuccess) return TATRG_EHIP;
+  hipMemcpy(h->acc, &acc, sizeof(double), hipMemcpyHostToDevice);
+  h->step = step;
+  if (!hip_ok(h, "set_state")) return TATRG_EHIP;
+  return TATRG_OK;
+}
+
+const char* tatrg_last_error(const tatrg_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+void tatrg_destroy(tatrg_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// FP64 GEMM on the CDNA4 FP64 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// Every contraction of the Triad-ATRG step (Section 2: bond swap products, Grams of the
+// isometries and squeezers, triad tensors and the O(r^2 chi^7) contraction of Eqs. (makeMG),
+// (makeMH)) is issued as a strided-batched row-major GEMM after leg reordering.
+//
+// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) computes a 128 x 128 tile of C;
+// each wave owns 64 x 64 = 4 x 4 MFMA blocks of 16 x 16 held in 64 accumulator doubles per
+// lane.  K advances in steps of 16 through a double-buffered LDS stage (A as [k][m], B as
+// [k][n], so MFMA fragments are read with unit stride); the next stage's global loads are
+// issued before the MFMAs of the current one.  Optional split-K: blockIdx.z enumerates
+// (batch, K part) and parts are summed afterwards in a fixed order.
+#include "common.h"
+
+namespace tatrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
+
+struct KArgs {
+  GemmArgs g;
+  int kparts;       // 1 = no split
+  int64_t kchunk;   // K elements per part
+  double* partial;  // kparts > 1: output [batch][kparts][M][N]
+};
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
+  const GemmArgs& g = ka.g;
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t z = blockIdx.z;
+  const int64_t b = z / ka.kparts;
+  const int64_t p = z - b * ka.kparts;
+  const int64_t kb = p * ka.kchunk;
+  const int64_t K = (ka.kparts > 1) ? ((g.K - kb) < ka.kchunk ? (g.K - kb) : ka.kchunk) : g.K;
+
+  const double* A = g.A + b * g.sA + (g.ta ? kb * g.lda : kb);
+  const double* B = g.B + b * g.sB + (g.tb ? kb : kb * g.ldb);
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t M = g.M, N = g.N;
+
+  double ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    if (!g.ta) {
+      const int r = tid >> 1, kc = (tid & 1) * 8;
+      const int64_t m = m0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t k = k0 + kc + i;
+        ra[i] = (m < M && k < K) ? A[m * g.lda + k] : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, mc = (tid & 15) * 8;
+      const int64_t k = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t m = m0 + mc + i;
+        ra[i] = (m < M && k < K) ? A[k * g.lda + m] : 0.0;
+      }
+    }
+    if (!g.tb) {
+      const int kk = tid >> 4, nc = (tid & 15) * 8;
+      const int64_t k = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t n = n0 + nc + i;
+        rb[i] = (n < N && k < K) ? B[k * g.ldb + n] : 0.0;
+      }
+    } else {
+      const int r = tid >> 1, kc = (tid & 1) * 8;
+      const int64_t n = n0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t k = k0 + kc + i;
+        rb[i] = (n < N && k < K) ? B[n * g.ldb + k] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if (!g.ta) {
+      const int r = tid >> 1, kc = (tid & 1) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[buf][kc + i][r] = ra[i];
+    } else {
+      const int kk = tid >> 4, mc = (tid & 15) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[buf][kk][mc + i] = ra[i];
+    }
+    if (!g.tb) {
+      const int kk = tid >> 4, nc = (tid & 15) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][kk][nc + i] = rb[i];
+    } else {
+      const int r = tid >> 1, kc = (tid & 1) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][kc + i][r] = rb[i];
+    }
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = As[cur][kk + (lane >> 4)][wm * 64 + t * 16 + (lane & 15)];
+        bb[t] = Bs[cur][kk + (lane >> 4)][wn * 64 + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // D fragment: lane l, element v holds row 4*(l/16)+v, column l%16 of a 16 x 16 block.
+  double* C;
+  int64_t ldc;
+  double alpha, beta;
+  if (ka.kparts > 1) {
+    C = ka.partial + (b * ka.kparts + p) * M * N;
+    ldc = N;
+    alpha = 1.0;
+    beta = 0.0;
+  } else {
+    C = g.C + b * g.sC;
+    ldc = g.ldc;
+    alpha = g.alpha;
+    beta = g.beta;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double val = alpha * acc[i][j][v];
+          if (beta != 0.0) val += beta * C[row * ldc + col];
+          C[row * ldc + col] = val;
+        }
+      }
+}
+
+// C[b] = alpha * sum_p partial[b][p] + beta * C[b], parts summed in increasing p.
+__global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64_t N,
+                              int64_t ldc, int64_t sC, int kparts, int64_t batch, double alpha,
+                              double beta) {
+  const int64_t total = batch * M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / (M * N);
+    const int64_t r = idx - b * M * N;
+    const int64_t i = r / N, j = r - (r / N) * N;
+    const double* pp = partial + b * kparts * M * N + r;
+    double s = 0.0;
+    for (int p = 0; p < kparts; ++p) s += pp[(int64_t)p * M * N];
+    double* c = C + b * sC + i * ldc + j;
+    double val = alpha * s;
+    if (beta != 0.0) val += beta * *c;
+    *c = val;
+  }
+}
+
+void launch(const KArgs& ka, hipStream_t st) {
+  const GemmArgs& g = ka.g;
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
+            (unsigned)(g.batch * ka.kparts));
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, st, ka);
+}
+
+}  // namespace
+
+void gemm_f64(const GemmArgs& g, hipStream_t st) {
+  KArgs ka{g, 1, g.K, nullptr};
+  launch(ka, st);
+}
+
+void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t st) {
+  if (parts <= 1 || g.K <= BK) {
+    gemm_f64(g, st);
+    return;
+  }
+  int64_t chunk = (g.K + parts - 1) / parts;
+  chunk = ((chunk + BK - 1) / BK) * BK;
+  const int used = (int)((g.K + chunk - 1) / chunk);
+  KArgs ka{g, used, chunk, partial};
+  launch(ka, st);
+  const int64_t total = g.batch * g.M * g.N;
+  const int threads = 256;
+  int64_t blocks = (total + threads - 1) / threads;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, partial, g.C,
+                     g.M, g.N, g.ldc, g.sC, used, g.batch, g.alpha, g.beta);
+}
+
+}  // namespace tatrg

@@ -1,0 +1,210 @@
+// Memory-bound helper kernels: Philox Gaussian sketches, leg permutations, scaling, copies.
+#include "common.h"
+
+namespace tatrg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned grid_for(int64_t n, int tpb = TPB) {
+  int64_t b = (n + tpb - 1) / tpb;
+  if (b < 1) b = 1;
+  if (b > 1048576) b = 1048576;
+  return (unsigned)b;
+}
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): per round
+// (hi0,lo0) = M0*c0, (hi1,lo1) = M1*c2, c = (hi1^c1^k0, lo1, hi0^c3^k1, lo0); the key is
+// advanced by the Weyl increments between rounds.
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Element pair p = e >> 1 of stream (seed, step, site): counter (lo(p), hi(p), step, site),
+// key (lo(seed), hi(seed)); two 53-bit uniforms, Box-Muller (cos for even e, sin for odd e).
+__global__ void philox_gauss_kernel(double* out, int64_t rows, int64_t cols, int64_t ld,
+                                    int transposed, uint32_t k0, uint32_t k1, uint32_t step,
+                                    uint32_t site) {
+  const int64_t total = rows * cols;
+  const int64_t npairs = (total + 1) >> 1;
+  for (int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pr < npairs;
+       pr += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)pr, (uint32_t)((uint64_t)pr >> 32), step, site};
+    philox10(c, k0, k1);
+    const double two26 = 67108864.0;
+    const double scale = 1.1102230246251565e-16;  // 2^-53
+    const double u1 = ((double)(c[0] >> 5) * two26 + (double)(c[1] >> 6) + 1.0) * scale;
+    const double u2 = ((double)(c[2] >> 5) * two26 + (double)(c[3] >> 6)) * scale;
+    const double r = sqrt(-2.0 * log(u1));
+    const double th = 6.283185307179586 * u2;
+    const double g[2] = {r * cos(th), r * sin(th)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t e = 2 * pr + h;
+      if (e < total) {
+        const int64_t i = e / cols, j = e - (e / cols) * cols;
+        if (transposed)
+          out[j * ld + i] = g[h];
+        else
+          out[i * ld + j] = g[h];
+      }
+    }
+  }
+}
+
+struct PermArgs {
+  int rank;
+  int64_t out_dims[6];
+  int64_t in_stride_for_out[6];  // input stride of output dimension k
+};
+
+__global__ void permute_kernel(const double* __restrict__ in, double* __restrict__ out,
+                               PermArgs pa, int64_t total) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, off = 0;
+    for (int k = pa.rank - 1; k >= 0; --k) {
+      const int64_t d = pa.out_dims[k];
+      const int64_t q = rem / d;
+      off += (rem - q * d) * pa.in_stride_for_out[k];
+      rem = q;
+    }
+    out[idx] = in[off];
+  }
+}
+
+__global__ void scale_cols_kernel(double* x, const double* s, int64_t rows, int64_t cols,
+                                  int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / cols, j = idx - (idx / cols) * cols;
+    x[i * ld + j] *= s[j];
+  }
+}
+
+__global__ void copy_kernel(double* y, const double* x, int64_t n) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    y[idx] = x[idx];
+}
+
+__global__ void zero_kernel(double* y, int64_t n) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    y[idx] = 0.0;
+}
+
+__global__ void identity_kernel(double* x, int n, int64_t ld) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx - (idx / n) * n;
+    x[i * ld + j] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void symmetrize_kernel(double* A, int n, int batch) {
+  const int64_t per = (int64_t)n * n;
+  const int64_t total = per * batch;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / per, r = idx - b * per;
+    const int64_t i = r / n, j = r - (r / n) * n;
+    if (j > i) {
+      double* M = A + b * per;
+      const double v = 0.5 * (M[i * n + j] + M[j * n + i]);
+      M[i * n + j] = v;
+      M[j * n + i] = v;
+    }
+  }
+}
+
+__global__ void transpose_batched_kernel(const double* in, double* out, int rows, int cols,
+                                         int batch) {
+  const int64_t per = (int64_t)rows * cols;
+  const int64_t total = per * batch;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / per, r = idx - b * per;
+    const int64_t i = r / cols, j = r - (r / cols) * cols;
+    out[b * per + j * rows + i] = in[idx];
+  }
+}
+
+}  // namespace
+
+void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
+                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st) {
+  const int64_t npairs = (rows * cols + 1) / 2;
+  hipLaunchKernelGGL(philox_gauss_kernel, dim3(grid_for(npairs)), dim3(TPB), 0, st, out, rows,
+                     cols, ld, transposed ? 1 : 0, (uint32_t)seed, (uint32_t)(seed >> 32), step,
+                     site);
+}
+
+void permute(const double* in, double* out, int rank, const int64_t* dims, const int* perm,
+             hipStream_t st) {
+  PermArgs pa;
+  pa.rank = rank;
+  int64_t in_stride[6];
+  int64_t s = 1;
+  for (int k = rank - 1; k >= 0; --k) {
+    in_stride[k] = s;
+    s *= dims[k];
+  }
+  for (int k = 0; k < rank; ++k) {
+    pa.out_dims[k] = dims[perm[k]];
+    pa.in_stride_for_out[k] = in_stride[perm[k]];
+  }
+  hipLaunchKernelGGL(permute_kernel, dim3(grid_for(s)), dim3(TPB), 0, st, in, out, pa, s);
+}
+
+void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t ld,
+                hipStream_t st) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(rows * cols)), dim3(TPB), 0, st, x, s,
+                     rows, cols, ld);
+}
+
+void copy(double* y, const double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(TPB), 0, st, y, x, n);
+}
+
+void zero(double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(TPB), 0, st, x, n);
+}
+
+void identity(double* x, int n, int64_t ld, hipStream_t st) {
+  hipLaunchKernelGGL(identity_kernel, dim3(grid_for((int64_t)n * n)), dim3(TPB), 0, st, x, n,
+                     ld);
+}
+
+void symmetrize(double* A, int n, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_for((int64_t)n * n * batch)), dim3(TPB), 0,
+                     st, A, n, batch);
+}
+
+void transpose_batched(const double* in, double* out, int rows, int cols, int batch,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(transpose_batched_kernel, dim3(grid_for((int64_t)rows * cols * batch)),
+                     dim3(TPB), 0, st, in, out, rows, cols, batch);
+}
+
+}  // namespace tatrg

@@ -1,0 +1,78 @@
+// Kernel-level entry points for parity tests (include/tatrg_testing.h).
+#include "common.h"
+#include "../../include/tatrg_testing.h"
+
+using namespace tatrg;
+
+static int launched() { return hipGetLastError() == hipSuccess ? 0 : -3; }
+
+extern "C" {
+
+int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int64_t N,
+                    int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
+                    double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
+                    int64_t sC, int parts, double* partial, void* stream) {
+  if (!A || !B || !C || M < 0 || N < 0 || K < 0 || batch < 1) return -1;
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = sA; g.ta = ta != 0;
+  g.B = B; g.ldb = ldb; g.sB = sB; g.tb = tb != 0;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.alpha = alpha; g.beta = beta; g.batch = batch;
+  if (parts > 1) {
+    if (!partial) return -1;
+    gemm_f64_splitk(g, parts, partial, (hipStream_t)stream);
+  } else {
+    gemm_f64(g, (hipStream_t)stream);
+  }
+  return launched();
+}
+
+size_t tatrg_test_tsqr_ws(int64_t m, int n) {
+  if (n < 1 || n > 96 || m < n) return 0;
+  return tsqr_ws_doubles(m, n);
+}
+
+int tatrg_test_tsqr(double* Y, int64_t m, int n, int64_t ld, double* R, double* ws,
+                    void* stream) {
+  if (!Y || !ws || n < 1 || n > 96 || m < n || ld < n) return -1;
+  tsqr(Y, m, n, ld, R, ws, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_svd(const double* A, double* U, double* S, double* V, int n, int batch,
+                   void* stream) {
+  if (!A || !U || !S || !V || n < 1 || n > 96 || batch < 1) return -1;
+  jacobi_svd(A, U, S, V, n, batch, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag,
+                        void* stream) {
+  if (!A || !flag || n < 1 || batch < 1) return -1;
+  cholesky_shifted(A, n, batch, shift_rel, flag, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,
+                      uint32_t site, void* stream) {
+  if (!out || rows < 1 || cols < 1) return -1;
+  philox_gaussian(out, rows, cols, cols, false, seed, step, site, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_permute(const double* in, double* out, int rank, const int64_t* dims,
+                       const int* perm, void* stream) {
+  if (!in || !out || rank < 1 || rank > 6 || !dims || !perm) return -1;
+  permute(in, out, rank, dims, perm, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_gauge(const double* s, const double* P, double* O, int n, int n_probes,
+                     double tau_null, double tau_deg, void* stream) {
+  if (!s || !P || !O || n < 1 || n_probes < 1 || n_probes > 8) return -1;
+  gauge_rotation(s, P, O, n, n_probes, tau_null, tau_deg, (hipStream_t)stream);
+  return launched();
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""Kernel-level parity of libtatrg on the GPU against float64 numpy / oracle references.
+
+Every call goes through the C ABI (include/tatrg_testing.h) via the ctypes binding.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2412_14104_amd as pkg
+    return pkg.lib
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def gemm_bound(a, b, k):
+    return 4 * np.finfo(float).eps * (k + 2) * (np.abs(a) @ np.abs(b)) + 1e-300
+
+
+GEMM_CASES = [
+    (1, 1, 1, False, False), (17, 33, 5, False, False), (128, 128, 16, False, False),
+    (200, 130, 70, True, False), (130, 200, 70, False, True), (257, 300, 1000, True, True),
+    (64, 3, 4096, False, False), (5, 700, 33, True, False),
+]
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb", GEMM_CASES)
+def test_gemm_f64_matches_numpy(lib, m, n, k, ta, tb):
+    rng = np.random.default_rng(m * 1000 + n + k)
+    batch = 3
+    a = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    b = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    c0 = rng.standard_normal((batch, m, n))
+    da, db, dc = dev(a), dev(b), dev(c0)
+    rc = lib.tatrg_test_gemm(vp(da), vp(db), vp(dc), m, n, k, a.shape[2], b.shape[2], n,
+                             int(ta), int(tb), 0.75, -0.5, batch, a[0].size, b[0].size,
+                             c0[0].size, 1, None, stream())
+    assert rc == 0
+    got = host(dc)
+    for i in range(batch):
+        aa = a[i].T if ta else a[i]
+        bb = b[i].T if tb else b[i]
+        ref = 0.75 * aa @ bb - 0.5 * c0[i]
+        bound = 0.75 * gemm_bound(aa, bb, k) + 0.5 * np.abs(c0[i]) * 1e-16
+        assert np.all(np.abs(got[i] - ref) <= bound), (i, np.abs(got[i] - ref).max())
+
+
+def test_gemm_split_k_is_deterministic_and_correct(lib):
+    rng = np.random.default_rng(5)
+    m, n, k, parts = 40, 24, 50000, 16
+    a = rng.standard_normal((m, k))
+    b = rng.standard_normal((k, n))
+    da, db = dev(a), dev(b)
+    part = torch.empty(parts * m * n, dtype=torch.float64, device="cuda")
+    outs = []
+    for _ in range(2):
+        dc = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+        assert lib.tatrg_test_gemm(vp(da), vp(db), vp(dc), m, n, k, k, n, n, 0, 0, 1.0, 0.0, 1,
+                                   0, 0, 0, parts, vp(part), stream()) == 0
+        outs.append(host(dc))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.all(np.abs(outs[0] - a @ b) <= gemm_bound(a, b, k))
+
+
+TSQR_CASES = [(10, 1), (100, 7), (1000, 32), (5000, 96), (300000, 32), (120000, 96), (96, 96)]
+
+
+@pytest.mark.parametrize("m,n", TSQR_CASES)
+def test_tsqr_orthonormal_factor(lib, m, n):
+    rng = np.random.default_rng(m + n)
+    y = rng.standard_normal((m, n)) * np.logspace(0, -8, n)[None, :]
+    dy = dev(y)
+    ws = torch.empty(lib.tatrg_test_tsqr_ws(m, n), dtype=torch.float64, device="cuda")
+    dr = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_tsqr(vp(dy), m, n, n, vp(dr), vp(ws), stream()) == 0
+    q, r = host(dy), host(dr)
+    assert np.abs(q.T @ q - np.eye(n)).max() < 1e-13 * max(1, np.sqrt(m) / 100)
+    assert np.abs(np.tril(r, -1)).max() == 0.0
+    assert np.abs(q @ r - y).max() < 1e-14 * np.abs(y).max() * np.sqrt(n)
+    # same span as LAPACK's factor
+    qref, _ = np.linalg.qr(y)
+    assert np.abs(np.abs(np.linalg.svd(q.T @ qref, compute_uv=False)) - 1).max() < 1e-9
+
+
+def test_tsqr_rank_deficient_panel(lib):
+    rng = np.random.default_rng(11)
+    m, n = 50000, 40
+    y = rng.standard_normal((m, n))
+    y[:, 3] = 0.0
+    y[:, 10] = y[:, 2] * 2.0
+    y[:, 20:30] = 0.0
+    y[:1000, :] = 0.0
+    dy = dev(y)
+    ws = torch.empty(lib.tatrg_test_tsqr_ws(m, n), dtype=torch.float64, device="cuda")
+    dr = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_tsqr(vp(dy), m, n, n, vp(dr), vp(ws), stream()) == 0
+    q, r = host(dy), host(dr)
+    assert np.abs(q.T @ q - np.eye(n)).max() < 1e-13
+    assert np.abs(q @ r - y).max() < 1e-13 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("n", [2, 7, 32, 48, 96])
+def test_jacobi_svd_matches_lapack(lib, n):
+    rng = np.random.default_rng(n)
+    u0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    v0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sv = np.logspace(0, -12, n)
+    a = np.stack([u0 @ np.diag(sv) @ v0.T, rng.standard_normal((n, n))])
+    if n > 4:
+        a[1][:, -2:] = 0.0           # two zero singular values
+    da = dev(a)
+    du = torch.empty_like(da)
+    dv = torch.empty_like(da)
+    ds = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_svd(vp(da), vp(du), vp(ds), vp(dv), n, 2, stream()) == 0
+    u, s, v = host(du), host(ds), host(dv)
+    for i in range(2):
+        ref = np.linalg.svd(a[i], compute_uv=False)
+        assert np.abs(s[i] - ref).max() < 1e-14 * ref[0] * n
+        assert np.all(np.diff(s[i]) <= 0)
+        assert np.abs(u[i] @ np.diag(s[i]) @ v[i].T - a[i]).max() < 1e-14 * ref[0] * n
+        assert np.abs(v[i].T @ v[i] - np.eye(n)).max() < 1e-13
+        nz = s[i] > 1e-300
+        assert np.abs(u[i][:, nz].T @ u[i][:, nz] - np.eye(nz.sum())).max() < 1e-12
+    # graded spectrum: relative accuracy of the small singular values
+    assert np.abs(s[0] / sv - 1).max() < 1e-8
+
+
+@pytest.mark.parametrize("n,batch", [(5, 1), (64, 2), (100, 3), (1024, 2)])
+def test_cholesky_shifted(lib, n, batch):
+    rng = np.random.default_rng(n)
+    g = rng.standard_normal((batch, n, n + 3))
+    a = g @ g.transpose(0, 2, 1)
+    da = dev(a)
+    flag = torch.zeros(4, dtype=torch.int32, device="cuda")
+    shift = 1e-13
+    assert lib.tatrg_test_cholesky(vp(da), n, batch, shift, vp(flag), stream()) == 0
+    low = host(da)
+    assert host(flag)[0] == 0
+    for i in range(batch):
+        ref = a[i] + shift * np.trace(a[i]) * np.eye(n)
+        assert np.abs(np.triu(low[i], 1)).max() == 0.0
+        assert np.abs(low[i] @ low[i].T - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_cholesky_flags_indefinite_matrix(lib):
+    a = -np.eye(8)
+    da = dev(a)
+    flag = torch.zeros(4, dtype=torch.int32, device="cuda")
+    assert lib.tatrg_test_cholesky(vp(da), 8, 1, 0.0, vp(flag), stream()) == 0
+    assert host(flag)[0] == 1
+
+
+def test_philox_sketch_matches_oracle(lib):
+    from oracle import philox
+    for (rows, cols, seed, step, site) in [(7, 5, 0, 0, 0), (1000, 96, 0, 39, 0),
+                                           (33, 17, 2 ** 40 + 7, 3, 9)]:
+        out = torch.empty((rows, cols), dtype=torch.float64, device="cuda")
+        assert lib.tatrg_test_philox(vp(out), rows, cols, seed, step, site, stream()) == 0
+        ref = philox.gaussian_matrix(seed, step, site, rows, cols)
+        got = host(out)
+        assert np.abs(got - ref).max() <= 8 * np.finfo(float).eps * max(1.0, np.abs(ref).max())
+
+
+def test_permute_is_exact(lib):
+    rng = np.random.default_rng(3)
+    for dims, perm in [((3, 4, 5), (2, 0, 1)), ((2, 3, 4, 5, 6), (1, 2, 4, 0, 3)),
+                       ((5, 1, 7, 2, 3, 2), (5, 4, 3, 2, 1, 0))]:
+        x = rng.standard_normal(dims)
+        dx = dev(x)
+        out = torch.empty(x.size, dtype=torch.float64, device="cuda")
+        d = (ctypes.c_int64 * len(dims))(*dims)
+        p = (ctypes.c_int * len(perm))(*perm)
+        assert lib.tatrg_test_permute(vp(dx), vp(out), len(dims), d, p, stream()) == 0
+        assert np.array_equal(host(out).reshape(x.transpose(perm).shape), x.transpose(perm))
+
+
+def test_gauge_rotation_matches_oracle(lib):
+    from oracle import tatrg as t
+    rng = np.random.default_rng(4)
+    s = np.array([5.0, 3.0, 3.0, 3.0, 1.0, 0.5, 0.5, 1e-14, 0.0])
+    p = rng.standard_normal((8, s.size))
+    o = torch.empty((s.size, s.size), dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_gauge(vp(dev(s)), vp(dev(p)), vp(o), s.size, 8, t.TAU_NULL, t.TAU_DEG,
+                                stream()) == 0
+    assert np.abs(host(o) - t.gauge_fix(s, p)).max() < 1e-14
