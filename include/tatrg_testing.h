@@ -28,6 +28,16 @@ int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int6
                     double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
                     int64_t sC, int parts, double* partial, void* stream);
 
+/* Split-bf16 GEMM (three bf16 planes per operand, six products, fp32 accumulation in windows
+ * of 128 along K summed in float64).  Same operand conventions as tatrg_test_gemm; ws holds
+ * tatrg_test_gemm_bf16x3_ws(...) doubles. */
+size_t tatrg_test_gemm_bf16x3_ws(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb,
+                                 int ta, int tb, int64_t batch, int64_t sA, int64_t sB);
+int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t M, int64_t N,
+                           int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
+                           double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
+                           int64_t sC, double* ws, void* stream);
+
 /* Doubles of workspace tatrg_test_tsqr needs for an m x n panel. */
 size_t tatrg_test_tsqr_ws(int64_t m, int n);
 
@@ -59,6 +69,17 @@ int tatrg_test_permute(const double* in, double* out, int rank, const int64_t* d
  * (n_probes x n). */
 int tatrg_test_gauge(const double* s, const double* P, double* O, int n, int n_probes,
                      double tau_null, double tau_deg, void* stream);
+
+/* Measurement hooks.  Live timing of the four contraction GEMMs of each step (the
+ * dominant kernels, Eqs. (makeMG)/(makeMH)): tatrg_profile_enable reserves event pairs for
+ * up to max_launches launches (0 turns timing off) and brackets each launch with HIP events
+ * on the handle's stream; tatrg_profile_read synchronises, returns the summed device time
+ * of the recorded launches, their count and the algorithmic flops of one launch
+ * (2 L^2 chi^5), and clears the record.  `h` is a tatrg_handle*. */
+struct tatrg_handle;
+int tatrg_profile_enable(struct tatrg_handle* h, int max_launches);
+int tatrg_profile_read(struct tatrg_handle* h, double* total_ms, int32_t* launches,
+                       double* flops_per_launch);
 
 #ifdef __cplusplus
 }

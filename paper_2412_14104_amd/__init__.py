@@ -27,7 +27,7 @@ class TatrgError(RuntimeError):
 
 def _load():
     if not os.path.exists(library_path):
-        raise ImportError("libtatrg.so is not built; run python -m paper_2412_14104_amd.build")
+        raise ImportError("libtatrg.so is not built; run python paper_2412_14104_amd/build.py")
     return ctypes.CDLL(library_path)
 
 
@@ -63,6 +63,12 @@ _SIGS = {
     "tatrg_test_gemm": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _i64, _i64, _i64,
                                        ctypes.c_int, ctypes.c_int, _dbl, _dbl, _i64, _i64,
                                        _i64, _i64, ctypes.c_int, _p, _p]),
+    "tatrg_test_gemm_bf16x3_ws": (ctypes.c_size_t, [_i64, _i64, _i64, _i64, _i64,
+                                                    ctypes.c_int, ctypes.c_int, _i64, _i64,
+                                                    _i64]),
+    "tatrg_test_gemm_bf16x3": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _i64, _i64, _i64,
+                                              ctypes.c_int, ctypes.c_int, _dbl, _dbl, _i64,
+                                              _i64, _i64, _i64, _p, _p]),
     "tatrg_test_tsqr_ws": (ctypes.c_size_t, [_i64, ctypes.c_int]),
     "tatrg_test_tsqr": (ctypes.c_int, [_p, _i64, ctypes.c_int, _i64, _p, _p, _p]),
     "tatrg_test_svd": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int, ctypes.c_int, _p]),
@@ -72,6 +78,8 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int), _p]),
     "tatrg_test_gauge": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _dbl,
                                         _p]),
+    "tatrg_profile_enable": (ctypes.c_int, [_p, ctypes.c_int]),
+    "tatrg_profile_read": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32), _dblp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -150,6 +158,16 @@ class Engine:
     def set_state(self, phi, psi, step, acc):
         _check(lib.tatrg_set_state(self.handle, ctypes.c_void_p(phi.data_ptr()),
                                    ctypes.c_void_p(psi.data_ptr()), step, acc), self.handle)
+
+    def profile_enable(self, max_launches):
+        _check(lib.tatrg_profile_enable(self.handle, max_launches), self.handle)
+
+    def profile_read(self):
+        """(summed device ms, launches, flops per launch) of the timed contraction GEMMs."""
+        ms, n, fl = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib.tatrg_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n),
+                                      ctypes.byref(fl)), self.handle)
+        return ms.value, n.value, fl.value
 
     def run(self, beta):
         """All n_steps steps; returns (f, ln Z / V)."""

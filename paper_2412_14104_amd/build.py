@@ -1,6 +1,6 @@
 """Build libtatrg.so (the HIP library behind include/tatrg.h) for gfx950, in-tree.
 
-    python -m paper_2412_14104_amd.build
+    python paper_2412_14104_amd/build.py     (does not import the package)
 """
 import os
 import subprocess
@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtatrg.so")
-SOURCES = ["gemm_f64.hip", "linalg.hip", "misc.hip", "engine.hip", "testing.hip"]
+SOURCES = ["gemm_f64.hip", "gemm_bf16x3.hip", "linalg.hip", "misc.hip", "engine.hip", "testing.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed fp32 instructions are disabled on the test machines
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -25,6 +25,8 @@ void gemm_f64(const GemmArgs& g, hipStream_t st);
 // products with i + j <= 2 are accumulated in fp32 on the bf16 MFMA units.  Same contract.
 void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
                  hipStream_t st);
+// Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes of both operands.
+size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
 
 // Long-K GEMM with small M x N: the K range is split into `parts` chunks written to
 // `partial` (parts * batch * M * N doubles) and summed in a fixed order (deterministic).

@@ -9,6 +9,7 @@
 // (S5) and the slot rotation that brings the next direction to slot 1 (S6).
 #include "common.h"
 #include "../../include/tatrg.h"
+#include "../../include/tatrg_testing.h"
 
 #include <cmath>
 #include <cstdio>
@@ -153,7 +154,8 @@ struct tatrg_handle {
   double *Xs, *Ys, *AP, *Ap, *APp, *rho, *UZ, *E, *F, *Gt, *H;
   double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm2, *pm3, *sq1, *sq2, *sq3, *sq4;
   double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
-  double *partial, *probe, *small;
+  double *partial, *probe, *small, *planes;
+  size_t planes_doubles;
   int* flag;
   double* acc;
   double* lnc;
@@ -163,6 +165,11 @@ struct tatrg_handle {
   size_t partial_doubles;
   // small buffers (carved from `small`)
   size_t tsqr_cap;
+  // live timing of the contraction GEMMs (the dominant kernels): event pairs on st
+  bool profile = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double flops_per_launch = 0.0;
   double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
   double *Ssq, *Usq, *Vsq, *Umat, *Vmat;
 };
@@ -175,7 +182,7 @@ bool valid(const tatrg_config* c) {
   if (c->r < 1 || c->q < 0 || c->q > 16) return false;
   if (c->n_steps < 1 || c->n_steps > 64) return false;
   if (c->batch != 1) return false;
-  if (c->precision != TATRG_FP64) return false;
+  if (c->precision != TATRG_FP64 && c->precision != TATRG_BF16X3) return false;
   const int64_t L = std::min<int64_t>((int64_t)c->r * c->chi, (int64_t)c->chi * c->chi);
   if (L > MAX_W) return false;
   return true;
@@ -247,6 +254,16 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->q2 = cv.take(L * n4); h->q3 = cv.take(L * n4);
   h->Qt = cv.take(L * L * n2);
   h->phin = cv.take(n5);
+  h->planes_doubles = 0;
+  h->planes = nullptr;
+  if (h->cfg.precision == TATRG_BF16X3) {
+    // bf16 planes of the two contraction GEMMs (E.FM4 and Qt^T.P)
+    GemmArgs g1 = G(c * L, L * n2, n2, nullptr, n2, false, nullptr, L * n2, false, nullptr, 0);
+    GemmArgs g2 = Gb(G(n2, n2, L * L, nullptr, n2, true, nullptr, n2, false, nullptr, 0), c, 0,
+                     L * L * n2, n4);
+    h->planes_doubles = std::max(gemm_bf16x3_ws_doubles(g1), gemm_bf16x3_ws_doubles(g2));
+    h->planes = cv.take(h->planes_doubles);
+  }
   h->partial_doubles = splitk_partial_doubles(d);
   h->partial = cv.take(h->partial_doubles);
   h->probe = cv.take((size_t)N_PROBES * n4);
@@ -281,6 +298,20 @@ bool hip_ok(tatrg_handle* h, const char* where) {
 }
 
 void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
+
+// The contraction GEMMs, bracketed by events when live timing is on.
+void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
+  const bool on = h->profile && h->ev_used + 2 <= (int)h->ev.size();
+  if (on) hipEventRecord(h->ev[h->ev_used], h->st);
+  if (h->cfg.precision == TATRG_BF16X3)
+    gemm_bf16x3(g, h->planes, h->planes_doubles, h->st);
+  else
+    gemm_f64(g, h->st);
+  if (on) {
+    hipEventRecord(h->ev[h->ev_used + 1], h->st);
+    h->ev_used += 2;
+  }
+}
 
 // Deterministic split-K for Grams with long K and a small output.
 void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
@@ -594,7 +625,7 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   // FM4[i4a][a][kX][g][k4]
   perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
   // P[(i1 kA)][(kX g k4)] = E[(i1 kA)][(i4a a)] FM4[(i4a a)][(kX g k4)]
-  gemm(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
+  gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
   // Qt[kA][kX][k2][k3]
   gemm(h, G(c * L, n2, c, I, c * L, true, S2, n2, false, h->q1, n2));        // [(i3a kA),(i2b k2)]
   gemm(h, G(L * n2, n2, c, h->q1, L * n2, true, S3, n2, false, h->q2, n2));  // [(kA i2b k2),(i3b k3)]
@@ -602,8 +633,8 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   gemm(h, G(L * n2, L, n2, h->q3, n2, false, J, L, false, h->q1, L));        // [(kA k2 k3), kX]
   perm(h, h->q1, h->Qt, {L, c, c, L}, {0, 3, 1, 2});                        // [kA,kX,k2,k3]
   // phin[i1][(k2 k3)][(g k4)] = Qt^T P[i1]
-  gemm(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0, L * L * n2,
-             d.n4));
+  gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0,
+                   L * L * n2, d.n4));
   // rotate: [i1,k2,k3,g,k4] -> [k2,k3,k4,i1,g]
   perm(h, h->phin, out, {c, c, c, c, c}, {1, 2, 4, 0, 3});
 }
@@ -720,8 +751,7 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
   if (k < 1 || w < k || w > MAX_W || m < w || n < w || lda < n) return TATRG_EINVAL;
   const int64_t cap = h->d.n4 * h->d.Ls;
   if (m * w > cap || n * w > cap) return TATRG_EINVAL;
-  if (tsqr_ws_doubles(m, w) > h->tsqr_cap || tsqr_ws_doubles(n, w) > h->tsqr_cap ||
-      n * k > h->d.n2 * h->d.c)
+  if (tsqr_ws_doubles(m, w) > h->tsqr_cap || tsqr_ws_doubles(n, w) > h->tsqr_cap)
     return TATRG_EINVAL;
   struct MOp : Op {
     tatrg_handle* h;
@@ -749,9 +779,8 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
   h->cfg.q = save_q;
   h->step = save_step;
   gemm_f64(G(m, k, w, h->P2, w, false, h->Uh, w, false, d_U, k), h->st);
-  // Vt = (Qb Vh[:, :k])^T
-  gemm_f64(G(n, k, w, h->P1, w, false, h->Vh, w, false, h->Usq, k), h->st);
-  transpose_batched(h->Usq, d_Vt, (int)n, k, 1, h->st);
+  // Vt = (Qb Vh[:, :k])^T = Vh[:, :k]^T Qb^T
+  gemm_f64(G(k, n, w, h->Vh, w, true, h->P1, w, true, d_Vt, n), h->st);
   hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, h->st, d_S, h->Sh, k);
   if (!hip_ok(h, "rsvd")) return TATRG_EHIP;
   return TATRG_OK;
@@ -858,6 +887,43 @@ tatrg_status tatrg_set_state(tatrg_handle* h, const double* d_phi, const double*
 
 const char* tatrg_last_error(const tatrg_handle* h) { return h ? h->err.c_str() : "null handle"; }
 
-void tatrg_destroy(tatrg_handle* h) { delete h; }
+int tatrg_profile_enable(tatrg_handle* h, int max_launches) {
+  if (!h || max_launches < 0) return -1;
+  for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  h->ev.clear();
+  h->ev_used = 0;
+  h->profile = max_launches > 0;
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -3;
+    h->ev.push_back(e);
+  }
+  const double L = h->d.L, c5 = (double)h->d.n5;
+  h->flops_per_launch = 2.0 * L * L * c5;  // each of the four contraction GEMMs
+  return 0;
+}
+
+int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
+                       double* flops_per_launch) {
+  if (!h || !total_ms || !launches || !flops_per_launch) return -1;
+  if (hipStreamSynchronize(h->st) != hipSuccess) return -3;
+  double t = 0.0;
+  for (int i = 0; i + 1 < h->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) != hipSuccess) return -3;
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = h->ev_used / 2;
+  *flops_per_launch = h->flops_per_launch;
+  h->ev_used = 0;
+  return 0;
+}
+
+void tatrg_destroy(tatrg_handle* h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  delete h;
+}
 
 }  // extern "C"

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     __syncthreads();
   }
 
-  // D fragment: lane l, element v holds row 4*(l/16)+v, column l%16 of a 16 x 16 block.
+  // D fragment of v_mfma_f64_16x16x4: lane l, element v holds row (l/16) + 4v, column l%16
+  // of the 16 x 16 block (checked against a host reference by the GEMM tests).
   double* C;
   int64_t ldc;
   double alpha, beta;
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
         const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (row < M && col < N) {
           double val = alpha * acc[i][j][v];

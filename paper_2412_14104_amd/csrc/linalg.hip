@@ -265,7 +265,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
       int best = x;
       for (int y = x + 1; y < ne; ++y)
         if (norms[order[y]] > norms[order[best]]) best = y;
-      const int tmp = order[x];
+      const int tmp = order[best];  // move the largest remaining to position x
       for (int y = best; y > x; --y) order[y] = order[y - 1];
       order[x] = tmp;
     }

@@ -28,6 +28,35 @@ int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int6
   return launched();
 }
 
+static GemmArgs mk(const double* A, const double* B, double* C, int64_t M, int64_t N,
+                   int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
+                   double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
+                   int64_t sC) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = sA; g.ta = ta != 0;
+  g.B = B; g.ldb = ldb; g.sB = sB; g.tb = tb != 0;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.alpha = alpha; g.beta = beta; g.batch = batch;
+  return g;
+}
+
+size_t tatrg_test_gemm_bf16x3_ws(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb,
+                                 int ta, int tb, int64_t batch, int64_t sA, int64_t sB) {
+  return gemm_bf16x3_ws_doubles(
+      mk(nullptr, nullptr, nullptr, M, N, K, lda, ldb, 0, ta, tb, 1, 0, batch, sA, sB, 0));
+}
+
+int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t M, int64_t N,
+                           int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
+                           double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
+                           int64_t sC, double* ws, void* stream) {
+  if (!A || !B || !C || !ws || M < 0 || N < 0 || K < 0 || batch < 1) return -1;
+  GemmArgs g = mk(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, batch, sA, sB, sC);
+  gemm_bf16x3(g, ws, gemm_bf16x3_ws_doubles(g), (hipStream_t)stream);
+  return launched();
+}
+
 size_t tatrg_test_tsqr_ws(int64_t m, int n) {
   if (n < 1 || n > 96 || m < n) return 0;
   return tsqr_ws_doubles(m, n);

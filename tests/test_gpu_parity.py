@@ -132,3 +132,19 @@ def test_standalone_rsvd(pkg):
     assert np.abs(s - ref).max() < 1e-12 * ref[0]
     recon = du.cpu().numpy() @ np.diag(s) @ dvt.cpu().numpy()
     assert np.abs(recon - a).max() < 1e-12 * np.abs(a).max()
+
+
+REL_F_BF16 = 1e-6     # free-energy parity of the split-bf16 contraction path
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_split_bf16_free_energy_matches_oracle(pkg, name):
+    g = golden(name)
+    run = g["runs"][0]
+    print("case", name, "bf16x3", flush=True)
+    eng = pkg.Engine(g["chi"], g["r"], g["q"], g["n_steps"], seed=g["seed"],
+                     precision=pkg.BF16X3)
+    f, _ = eng.run(run["beta"])
+    rel = abs(f - run["f"]) / abs(run["f"])
+    print("split-bf16 |df|/|f| =", rel, flush=True)
+    assert rel <= REL_F_BF16, rel
