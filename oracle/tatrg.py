@@ -33,7 +33,7 @@ SITE_PROBE_SQZ = {2: 9, 3: 10, 4: 11}
 
 N_PROBES = 8          # largest degenerate cluster whose basis is fixed by probes
 TAU_NULL = 1e-11      # singular values below TAU_NULL * s_max carry no gauge
-TAU_DEG = 1e-11       # neighbours closer than TAU_DEG * s_max form one cluster
+TAU_DEG = 1e-6        # neighbours closer than TAU_DEG * s_max form one cluster
 SQZ_CUTOFF = 1e-10    # squeezer modes with S < SQZ_CUTOFF * S_max are masked
 CHOL_SHIFT = 1e-13    # rho + CHOL_SHIFT * tr(rho) * I before Cholesky
 
@@ -121,9 +121,10 @@ def gauge_fix(s, probe_proj):
     """Orthogonal block-diagonal O that fixes the basis freedom of an SVD.
 
     READING (the paper is silent; needed so that seeded sketches of later steps do not depend
-    on the rounding of an SVD): singular vectors with s <= TAU_NULL*s_max carry no weight and
-    are left alone.  Runs of neighbours with s_j - s_{j+1} <= TAU_DEG*s_max form a cluster
-    [j0, j0+m).  With P = probe_proj[:m, j0:j0+m] (probe p against singular vector j), the
+    on the rounding of an SVD, nor on perturbations that split a degenerate multiplet):
+    singular vectors with s <= TAU_NULL*s_max carry no weight and are left alone.  Runs of
+    neighbours with s_j - s_{j+1} <= TAU_DEG*s_max form a cluster [j0, j0+m).  The callers
+    apply the rotation so that the represented tensor is unchanged for any O.  With P = probe_proj[:m, j0:j0+m] (probe p against singular vector j), the
     cluster is rotated by O_c where P^T = O_c R (QR, diag R >= 0), so that P O_c is lower
     triangular with a non-negative diagonal.  Clusters of more than N_PROBES vectors are left
     alone.  Returns O (n x n).
@@ -159,8 +160,10 @@ def probes(seed, step, site, n_rows):
 def canonicalize(phi, psi, seed, step):
     """T = Phi Psi^T = A s B^T with isometric A, B (canonical form, Section 2).
 
-    Thin QR of Phi and Psi, SVD of R_Phi R_Psi^T, gauge fixed with probes against A.
-    Returns A[f,a], s (normalised to |s|=1), B[b,a] and c = |T|_F.
+    Thin QR of Phi and Psi, SVD of R_Phi R_Psi^T, gauge fixed with probes against A: with the
+    rotation O, A' = A O, B' = B O and the weight matrix S' = O^T diag(s) O, so that
+    T = c A' S' B'^T exactly.  Returns A'[f,a], s (normalised to |s|=1), B'[b,a], c = |T|_F
+    and S' (normalised).
     """
     chi = phi.shape[-1]
     n = chi ** 4
@@ -174,16 +177,19 @@ def canonicalize(phi, psi, seed, step):
     a = a @ o
     b = (qs @ v) @ o
     c = float(np.sqrt(np.sum(s * s)))
-    return a.reshape((chi,) * 5), s / c, b.reshape((chi,) * 5), c
+    sn = s / c
+    smat = o.T @ (sn[:, None] * o)
+    return a.reshape((chi,) * 5), sn, b.reshape((chi,) * 5), c, smat
 
 
 # --------------------------------------------------------------------------- S1
-def bond_swap(a, s, b, ls, q, seed, step):
+def bond_swap(a, smat, b, ls, q, seed, step):
     """Bond swapping of the unit cell (Section 2, Eq. (1); cost row "Bond swapping" of Table 1).
 
     Cell of site n+1 (upper) and site n along direction 1, inner bond x = i1(n) = j1(n+1).
     READING: s is placed on both sides of the middle so that A(n+1) and D = B(n) stay
-    isometric:  M[(alpha,f'),(beta,b')] = sum_x s_alpha B[x,b',alpha] A[x,f',beta] s_beta,
+    isometric:  M[(alpha,f'),(beta,b')] = sum_x (B S)[x,b',alpha] (A S)[x,f',beta], with the
+    weight matrix S of the canonical form (diag(s) up to the gauge rotation),
     with f' = (f2 f3 f4) of site n and b' = (b2 b3 b4) of site n+1.  Its rank-chi
     randomized SVD M ~= X sigma Y^T gives Gamma = A X sigma Y D.  Omega is indexed by the
     columns (beta, b') of M.
@@ -192,8 +198,8 @@ def bond_swap(a, s, b, ls, q, seed, step):
     chi = a.shape[0]
     n3 = chi ** 3
     n2 = chi * chi
-    at = (a * s).reshape(chi, n3, chi)      # A~[x, f', beta]
-    bt = (b * s).reshape(chi, n3, chi)      # B~[x, b', alpha]
+    at = (a.reshape(-1, chi) @ smat).reshape(chi, n3, chi)      # A~[x, f', beta]
+    bt = (b.reshape(-1, chi) @ smat).reshape(chi, n3, chi)      # B~[x, b', alpha]
     at_f = at.transpose(1, 0, 2).reshape(n3, n2)    # [f', (x beta)]
     bt_x = bt.transpose(0, 2, 1).reshape(n2, n3)    # [(x alpha), b']
     # Rows of the left space are stored in (f', alpha) order; a row permutation does not
@@ -296,12 +302,12 @@ def squeezer_pair(rho_l, rho_r, chi, lw, q, seed, step, site, probe_site):
     u, s_, v = rsvd_dense(c, chi, w, q, seed, step, site)
     pw = probes(seed, step, probe_site, n2)
     o = gauge_fix(s_, pw @ v)
-    u, v = u @ o, v @ o
     smax = s_[0] if s_.size else 0.0
     keep = s_ > SQZ_CUTOFF * smax
     d = np.where(keep, 1.0 / np.sqrt(np.where(keep, s_, 1.0)), 0.0)
-    m_sq = (r_r.T @ v) * d[None, :]
-    n_sq = (d[:, None] * u.T) @ r_l
+    # rotate after the S^-1/2 weights: M N = R_R^T V S^-1 U^T R_L for any O
+    m_sq = ((r_r.T @ v) * d[None, :]) @ o
+    n_sq = o.T @ ((d[:, None] * u.T) @ r_l)
     return m_sq, n_sq, s_
 
 
@@ -408,8 +414,8 @@ def step(phi, psi, k, chi, r, q, seed):
     """One coarse-graining step along slot 1 (Section 2 and Fig. 3 flow): canonical form,
     bond swap, isometries, triad tensors, squeezers, contraction, slot rotation."""
     lw, ls = widths(chi, r)
-    a, s, b, c = canonicalize(phi, psi, seed, k)
-    x, sig, y = bond_swap(a, s, b, ls, q, seed, k)
+    a, s, b, c, smat = canonicalize(phi, psi, seed, k)
+    x, sig, y = bond_swap(a, smat, b, ls, q, seed, k)
     iso = isometries(a, x, sig, y, b, lw, q, seed, k)
     e, f, g, h, ua, ux, uy, ud = triad(a, x, sig, y, b, iso)
     sq = squeezers(e, f, g, h, ua, ux, uy, ud, lw, q, seed, k)
@@ -422,9 +428,9 @@ def step(phi, psi, k, chi, r, q, seed):
 def finish(phi, psi, seed, n_steps):
     """Trace of the last tensor on the 1x1x1x1 periodic lattice, after one more canonical
     normalisation: returns (ln c_N, tTr of the normalised tensor)."""
-    a, s, b, c = canonicalize(phi, psi, seed, n_steps)
+    a, s, b, c, smat = canonicalize(phi, psi, seed, n_steps)
     chi = a.shape[-1]
-    ttr = float(np.sum(a.reshape(-1, chi) * s[None, :] * b.reshape(-1, chi)))
+    ttr = float(np.sum((a.reshape(-1, chi) @ smat) * b.reshape(-1, chi)))
     return math.log(c), ttr
 
 

@@ -119,15 +119,34 @@ def test_canonical_form_is_gauge_fixed_including_degenerate_clusters():
     o, _ = np.linalg.qr(rng.standard_normal((chi, chi)))
     phi2 = (phi.reshape(n, chi) @ o).reshape((chi,) * 5)
     psi2 = (psi.reshape(n, chi) @ o).reshape((chi,) * 5)
-    a1, s1, b1, c1 = t.canonicalize(phi, psi, 0, 4)
-    a2, s2, b2, c2 = t.canonicalize(phi2, psi2, 0, 4)
+    a1, s1, b1, c1, m1 = t.canonicalize(phi, psi, 0, 4)
+    a2, s2, b2, c2, m2 = t.canonicalize(phi2, psi2, 0, 4)
     assert abs(c1 - math.sqrt(17.0)) < 1e-13
     assert np.allclose(s1, s / math.sqrt(17.0), atol=1e-15)
     assert np.abs(a1 - a2).max() < 1e-12 and np.abs(b1 - b2).max() < 1e-12
     # T is reproduced and A, B are isometric
-    tt = (a1.reshape(n, chi) * s1) @ b1.reshape(n, chi).T * c1
+    assert np.abs(m1 - m2).max() < 1e-13
+    tt = (a1.reshape(n, chi) @ m1) @ b1.reshape(n, chi).T * c1
     assert np.abs(tt - phi.reshape(n, chi) @ psi.reshape(n, chi).T).max() < 1e-13
     assert np.abs(a1.reshape(n, chi).T @ a1.reshape(n, chi) - np.eye(chi)).max() < 1e-14
+
+
+def test_gauge_rotation_keeps_the_tensor_for_a_split_cluster():
+    """A cluster of unequal but close singular values is rotated into the probe basis; the
+    weight matrix S' = O^T diag(s) O keeps c A' S' B'^T equal to T exactly."""
+    rng = np.random.default_rng(8)
+    chi = 3
+    n = chi ** 4
+    qa, _ = np.linalg.qr(rng.standard_normal((n, chi)))
+    qb, _ = np.linalg.qr(rng.standard_normal((n, chi)))
+    s = np.array([3.0, 2.0, 2.0 - 1e-7])
+    phi = (qa * s).reshape((chi,) * 5)
+    psi = qb.reshape((chi,) * 5)
+    a, sn, b, c, smat = t.canonicalize(phi, psi, 0, 1)
+    assert np.abs(smat - np.diag(sn)).max() > 1e-12          # the cluster was rotated
+    tt = c * (a.reshape(n, chi) @ smat) @ b.reshape(n, chi).T
+    assert np.abs(tt - phi.reshape(n, chi) @ psi.reshape(n, chi).T).max() < 1e-13
+    assert np.allclose(np.linalg.eigvalsh(smat)[::-1], sn, atol=1e-15)
 
 
 # ----------------------------------------------------------------------------- swap
@@ -147,7 +166,7 @@ def test_bond_swap_matches_dense_svd_of_the_cell_middle():
     chi = 3
     a, s, b = _random_canonical(chi, rng)
     m = np.einsum("xpqra,xfghb,a,b->afghbpqr", b, a, s, s).reshape(chi ** 4, chi ** 4)
-    x, sig, y = t.bond_swap(a, s, b, chi ** 4, 1, 0, 0)
+    x, sig, y = t.bond_swap(a, np.diag(s), b, chi ** 4, 1, 0, 0)
     ref = np.linalg.svd(m, compute_uv=False)
     assert np.allclose(sig, ref[:chi], rtol=1e-12)
     # X sigma Y^T is the best rank-chi approximation of M
@@ -164,7 +183,7 @@ def test_isometry_grams_are_grams_of_the_cell():
     rng = np.random.default_rng(5)
     chi = 3
     a, s, b = _random_canonical(chi, rng)
-    x, sig, y = t.bond_swap(a, s, b, chi ** 4, 1, 0, 0)
+    x, sig, y = t.bond_swap(a, np.diag(s), b, chi ** 4, 1, 0, 0)
     dbg = {}
     iso = t.isometries(a, x, sig, y, b, 9, 1, 0, 0, debug=dbg)
     axs = np.einsum("ijklA,Apqrg,g->ijklpqrg", a, x, sig)       # f(n+1), f'(n), gamma
@@ -206,7 +225,7 @@ def test_squeezer_grams_and_contraction_follow_their_definitions():
     rng = np.random.default_rng(7)
     chi, lw = 3, 4
     a, s, b = _random_canonical(chi, rng)
-    x, sig, y = t.bond_swap(a, s, b, chi ** 4, 1, 0, 0)
+    x, sig, y = t.bond_swap(a, np.diag(s), b, chi ** 4, 1, 0, 0)
     iso = t.isometries(a, x, sig, y, b, lw, 1, 0, 0)
     e, f, g, h, ua, ux, uy, ud = t.triad(a, x, sig, y, b, iso)
     dbg = {}
