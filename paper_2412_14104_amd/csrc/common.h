@@ -18,6 +18,10 @@ struct GemmArgs {
   double* C; int64_t ldc; int64_t sC;
   double alpha, beta;
   int64_t batch;
+  // Optional device-side predicate: when `cond` is set the launch does nothing unless
+  // (*cond != 0) == cond_when (lets a fallback path be launched without a host sync).
+  const int* cond = nullptr;
+  bool cond_when = false;
 };
 void gemm_f64(const GemmArgs& g, hipStream_t st);
 
@@ -38,7 +42,16 @@ void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t 
 // R factors.  On return Y holds Q (m x n) with Y_in = Q R; R (n x n) is written to R_out
 // when not null.  ws must hold tsqr_ws_doubles(m, n) doubles.
 size_t tsqr_ws_doubles(int64_t m, int n);
-void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st);
+void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st,
+          const int* run_if_set = nullptr);
+
+// Cholesky factor of an n x n Gram G = R^T R (n <= 96, one workgroup) with its inverse.
+// pass 0 factors G + shift_coef * tr(G) * I (the shifted first pass of CholeskyQR3) and fails
+// only on a non-finite or non-positive pivot; pass 1 raises *fail when a pivot is <= 1e-14 of
+// the largest diagonal entry; pass 2 (G close to the identity) raises it when a pivot leaves
+// (0.25, 4).  Does nothing when *fail is already set.
+void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
+              hipStream_t st, double shift_coef = 0.0);
 
 // ---------------------------------------------------------------------------- small dense
 // One-sided Jacobi SVD of `batch` square n x n matrices (n <= 96): A = U diag(S) V^T with S

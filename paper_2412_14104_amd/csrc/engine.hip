@@ -29,7 +29,7 @@ enum : uint32_t {
 };
 constexpr int N_PROBES = 8;
 constexpr double TAU_NULL = 1e-11;
-constexpr double TAU_DEG = 1e-11;
+constexpr double TAU_DEG = 1e-6;
 constexpr double SQZ_CUTOFF = 1e-10;
 constexpr double CHOL_SHIFT = 1e-13;
 constexpr int MAX_W = 96;
@@ -75,6 +75,16 @@ __global__ void normalize_kernel(double* s, int n, int k, double* acc, double* l
     for (int i = 0; i < n; ++i) rec[i] = s[i];
 }
 
+// Weight matrix of the gauge-rotated canonical form: S[i][j] = sum_k O[k][i] s[k] O[k][j].
+__global__ void smat_kernel(const double* O, const double* s, double* S, int n) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += O[k * n + i] * s[k] * O[k * n + j];
+    S[idx] = acc;
+  }
+}
+
 // d_k = S_k^-1/2 for S_k > cutoff * S_0, else 0.
 __global__ void mask_kernel(const double* S, double* D, int n, double cutoff) {
   const int i = threadIdx.x;
@@ -95,7 +105,7 @@ __global__ void trace_partial_kernel(const double* A, const double* s, const dou
   const int64_t total = rows * chi;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x)
-    acc += A[idx] * s[idx % chi] * B[idx];
+    acc += A[idx] * (s ? s[idx % chi] : 1.0) * B[idx];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int o = TPB / 2; o > 0; o >>= 1) {
@@ -150,7 +160,7 @@ struct tatrg_handle {
   bool initialized = false;
   std::vector<double> betas;
   // buffers
-  double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *t1, *t2, *tsqr_ws;
+  double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
   double *Xs, *Ys, *AP, *Ap, *APp, *rho, *UZ, *E, *F, *Gt, *H;
   double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm2, *pm3, *sq1, *sq2, *sq3, *sq4;
   double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
@@ -170,6 +180,7 @@ struct tatrg_handle {
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
   double flops_per_launch = 0.0;
+  double *Smat;
   double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
   double *Ssq, *Usq, *Vsq, *Umat, *Vmat;
 };
@@ -228,6 +239,8 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->X = cv.take(n5); h->Y = cv.take(n5);
   h->atf = cv.take(n5); h->btx = cv.take(n5);
   h->P1 = cv.take(n4 * Ls); h->P2 = cv.take(n4 * Ls);
+  h->P3 = cv.take(n4 * std::max(Ls, c));
+  h->Gq = cv.take(6 * (int64_t)MAX_W * MAX_W);
   h->t1 = cv.take(n3 * Ls); h->t2 = cv.take(n3 * Ls);
   const size_t tq = std::max(tsqr_ws_doubles(n4, (int)Ls),
                              std::max(tsqr_ws_doubles(n4, (int)c), tsqr_ws_doubles(n2, (int)L)));
@@ -275,6 +288,7 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->scal = cv.take(8);
   const int64_t w = std::max<int64_t>(Ls, L);
   h->s = cv.take(c); h->sig = cv.take(c);
+  h->Smat = cv.take(c * c);
   h->Rp = cv.take(c * c); h->Rs = cv.take(c * c); h->Cc = cv.take(c * c);
   h->Uc = cv.take(c * c); h->Vc = cv.take(c * c); h->Oc = cv.take(w * w);
   h->Pm = cv.take(N_PROBES * w);
@@ -298,6 +312,22 @@ bool hip_ok(tatrg_handle* h, const char* where) {
 }
 
 void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
+
+// dst[i][j] = src[i][j] for an m x n panel (leading dims lds, ldd).
+__global__ void copy_panel_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
+                                  int64_t m, int n) {
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx - (idx / n) * n;
+    dst[i * ldd + j] = src[i * lds + j];
+  }
+}
+void copy_panel(tatrg_handle* h, const double* src, int64_t lds, double* dst, int64_t ldd,
+                int64_t m, int n) {
+  hipLaunchKernelGGL(copy_panel_kernel, dim3(grid_for(m * n)), dim3(TPB), 0, h->st, src, lds,
+                     dst, ldd, m, n);
+}
 
 // The contraction GEMMs, bracketed by events when live timing is on.
 void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
@@ -326,6 +356,69 @@ void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
   gemm_f64_splitk(g, parts, h->partial, h->st);
 }
 
+// Orthonormal basis of a tall panel Y (m x n, ld), in place: Y <- Q with Y_in = Q R.
+// Shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020): a first
+// Cholesky pass on the Gram plus the shift 11 (mn + n(n+1)) u ||Y||^2 makes the panel
+// well conditioned, two plain passes make it orthonormal; Grams and products run on the
+// FP64 MFMA GEMM.  A panel that is rank deficient (a pivot of the second pass below 1e-14 of
+// the largest) is factorised by the Householder TSQR instead.  The choice is a device flag:
+// both paths are launched and each kernel of the unused one returns at once.  Both give the
+// same span up to rounding.
+void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_out) {
+  hipStream_t st = h->st;
+  int* fail = h->flag + 4;
+  const int64_t sq = (int64_t)MAX_W * MAX_W;
+  double* G1 = h->Gq;
+  double* R0 = h->Gq + sq;
+  double* R1 = h->Gq + 2 * sq;
+  double* R2 = h->Gq + 3 * sq;
+  double* Ri = h->Gq + 4 * sq;
+  double* Rt = h->Gq + 5 * sq;
+  const double shift = 11.0 * ((double)m * n + (double)n * (n + 1)) * 1.1102230246251565e-16;
+  zero((double*)fail, 1, st);
+  // pass 0 (shifted): Y -> P3 = Y R0^-1
+  gemm_long_k(h, G(n, n, m, Y, ld, true, Y, ld, false, G1, n));
+  chol_inv(G1, R0, Ri, n, 0, fail, st, shift);
+  gemm(h, G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n));
+  // pass 1: P3 -> Y = P3 R1^-1 (kept only when pass 2 succeeds; Y is overwritten here, so the
+  // fallback factorises the pass-0 panel P3 instead, which spans the same space)
+  gemm_long_k(h, G(n, n, m, h->P3, n, true, h->P3, n, false, G1, n));
+  chol_inv(G1, R1, Ri, n, 1, fail, st);
+  GemmArgs p1 = G(m, n, n, h->P3, n, false, Ri, n, false, Y, ld);
+  p1.cond = fail;
+  p1.cond_when = false;
+  gemm(h, p1);
+  // pass 2: Y -> P3 = Y R2^-1 -> copied back
+  GemmArgs g2 = G(n, n, m, Y, ld, true, Y, ld, false, G1, n);
+  gemm_long_k(h, g2);
+  chol_inv(G1, R2, Ri, n, 2, fail, st);
+  GemmArgs p2 = G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n);
+  p2.cond = fail;
+  p2.cond_when = false;
+  gemm(h, p2);
+  // Y <- P3: on success the orthonormal factor, on failure the pass-0 panel for the TSQR
+  copy_panel(h, h->P3, n, Y, ld, m, n);
+  if (R_out) {
+    // success: R = R2 R1 R0
+    GemmArgs a1 = G(n, n, n, R2, n, false, R1, n, false, Rt, n);
+    a1.cond = fail;
+    a1.cond_when = false;
+    gemm(h, a1);
+    GemmArgs a2 = G(n, n, n, Rt, n, false, R0, n, false, R_out, n);
+    a2.cond = fail;
+    a2.cond_when = false;
+    gemm(h, a2);
+  }
+  // failure: TSQR of the pass-0 panel (= Y R0^-1), then R = R_tsqr R0
+  tsqr(Y, m, n, ld, R_out ? Rt : nullptr, h->tsqr_ws, st, fail);
+  if (R_out) {
+    GemmArgs a3 = G(n, n, n, Rt, n, false, R0, n, false, R_out, n);
+    a3.cond = fail;
+    a3.cond_when = true;
+    gemm(h, a3);
+  }
+}
+
 void perm(tatrg_handle* h, const double* in, double* out, std::vector<int64_t> dims,
           std::vector<int> p) {
   permute(in, out, (int)dims.size(), dims.data(), p.data(), h->st);
@@ -348,17 +441,18 @@ void rsvd(tatrg_handle* h, Op& op, int64_t m, int64_t n, int w, int q, uint32_t 
   hipStream_t st = h->st;
   philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st);
   op.apply(Pb, Pa, w);
-  tsqr(Pa, m, w, w, nullptr, h->tsqr_ws, st);
+  orth(h, Pa, m, w, w, nullptr);
   for (int it = 0; it < h->cfg.q; ++it) {
     op.apply_t(Pa, Pb, w);
-    tsqr(Pb, n, w, w, nullptr, h->tsqr_ws, st);
+    orth(h, Pb, n, w, w, nullptr);
     op.apply(Pb, Pa, w);
-    tsqr(Pa, m, w, w, nullptr, h->tsqr_ws, st);
+    orth(h, Pa, m, w, w, nullptr);
   }
   (void)q;
+  (void)st;
   if (range_only) return;
   op.apply_t(Pa, Pb, w);
-  tsqr(Pb, n, w, w, h->Rb, h->tsqr_ws, st);
+  orth(h, Pb, n, w, w, h->Rb);
   transpose_batched(h->Rb, h->RbT, w, w, 1, st);
   jacobi_svd(h->RbT, h->Uh, h->Sh, h->Vh, w, 1, st);
 }
@@ -405,8 +499,8 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int c = d.c;
-  tsqr(h->phi, d.n4, c, c, h->Rp, h->tsqr_ws, st);
-  tsqr(h->psi, d.n4, c, c, h->Rs, h->tsqr_ws, st);
+  orth(h, h->phi, d.n4, c, c, h->Rp);
+  orth(h, h->psi, d.n4, c, c, h->Rs);
   gemm(h, G(c, c, c, h->Rp, c, false, h->Rs, c, true, h->Cc, c));
   jacobi_svd(h->Cc, h->Uc, h->s, h->Vc, c, 1, st);
   // probes against A = Q_Phi U
@@ -421,6 +515,8 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
   gemm(h, G(d.n4, c, c, h->psi, c, false, h->Uh, c, false, h->B, c));
   hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(64), 0, st, h->s, c, k, h->acc, h->lnc,
                      rec, h->flag);
+  // T = c A' S' B'^T with S' = O^T diag(s) O (exact for any gauge rotation O)
+  hipLaunchKernelGGL(smat_kernel, dim3(1), dim3(256), 0, st, h->Oc, h->s, h->Smat, c);
 }
 
 void bond_swap(tatrg_handle* h, double* rec) {
@@ -428,11 +524,9 @@ void bond_swap(tatrg_handle* h, double* rec) {
   hipStream_t st = h->st;
   const int c = d.c;
   const int w = d.Ls;
-  // A~ = A s, B~ = B s; atf = [f', (x beta)], btx = [(x alpha), b']
-  copy(h->Xs, h->A, d.n5, st);
-  scale_cols(h->Xs, h->s, d.n4, c, c, st);
-  copy(h->Ys, h->B, d.n5, st);
-  scale_cols(h->Ys, h->s, d.n4, c, c, st);
+  // A~ = A' S', B~ = B' S'; atf = [f', (x beta)], btx = [(x alpha), b']
+  gemm(h, G(d.n4, c, c, h->A, c, false, h->Smat, c, false, h->Xs, c));
+  gemm(h, G(d.n4, c, c, h->B, c, false, h->Smat, c, false, h->Ys, c));
   perm(h, h->Xs, h->atf, {c, d.n3, c}, {1, 0, 2});
   perm(h, h->Ys, h->btx, {c, d.n3, c}, {0, 2, 1});
   SwapOp op;
@@ -595,16 +689,17 @@ void squeezers(tatrg_handle* h, double* rec) {
                     pr_sites[mi], st);
     gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
     gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, st);
-    gemm(h, G(n2, c, c, h->Usq, c, false, h->Oc, c, false, h->Umat, c));
-    gemm(h, G(n2, c, c, h->Vsq, c, false, h->Oc, c, false, h->Vmat, c));
     hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, st, S, h->Dm, (int)c, SQZ_CUTOFF);
-    // M = R_R^T V D = Lr V D  (n2 x c), stored [u1][u2][k]
+    // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
+    // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
     double* M = h->Msq + mi * n2 * c;
-    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vmat, c, false, M, c));
-    scale_cols(M, h->Dm, n2, c, c, st);
-    // N = D U^T R_L = (Ll U D)^T  (c x n2), stored [k][v1][v2]
-    gemm(h, G(n2, c, n2, Ll, n2, false, h->Umat, c, false, h->Vsq, c));
-    scale_cols(h->Vsq, h->Dm, n2, c, c, st);
+    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
+    scale_cols(h->Vmat, h->Dm, n2, c, c, st);
+    gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
+    // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
+    gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
+    scale_cols(h->Umat, h->Dm, n2, c, c, st);
+    gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
     transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, st);
   }
 }
@@ -821,8 +916,10 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
   double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * d.c : nullptr;
   canonicalize(h, h->step, rec);
   const int nparts = 1024;
-  hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->A, h->s, h->B,
-                     d.n4, d.c, h->trace_part);
+  // tTr = sum_f (A' S' B'^T)[f, f]
+  gemm(h, G(d.n4, d.c, d.c, h->A, d.c, false, h->Smat, d.c, false, h->Xs, d.c));
+  hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->Xs,
+                     (const double*)nullptr, h->B, d.n4, d.c, h->trace_part);
   hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, h->st, h->trace_part, nparts,
                      h->scal + 1, h->flag);
   if (!hip_ok(h, "free_energy")) return TATRG_EHIP;

@@ -29,6 +29,7 @@ struct KArgs {
 
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const GemmArgs& g = ka.g;
+  if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
 // C[b] = alpha * sum_p partial[b][p] + beta * C[b], parts summed in increasing p.
 __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64_t N,
                               int64_t ldc, int64_t sC, int kparts, int64_t batch, double alpha,
-                              double beta) {
+                              double beta, const int* cond, int cond_when) {
+  if (cond && ((*cond != 0) != (cond_when != 0))) return;
   const int64_t total = batch * M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -221,7 +223,8 @@ void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t 
   int64_t blocks = (total + threads - 1) / threads;
   if (blocks > 65535) blocks = 65535;
   hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, partial, g.C,
-                     g.M, g.N, g.ldc, g.sC, used, g.batch, g.alpha, g.beta);
+                     g.M, g.N, g.ldc, g.sC, used, g.batch, g.alpha, g.beta, g.cond,
+                     g.cond_when ? 1 : 0);
 }
 
 }  // namespace tatrg

@@ -35,7 +35,8 @@ int leaf_rows(int n) {
 __global__ __launch_bounds__(256) void hh_factor_kernel(const double* src, int64_t rows,
                                                         int64_t lds, int b, int n, double* v,
                                                         int64_t ldv, double* tau,
-                                                        double* rstack) {
+                                                        double* rstack, const int* run_if) {
+  if (run_if && *run_if == 0) return;
   extern __shared__ double sm[];
   const int ld = n + 1;
   double* A = sm;
@@ -100,7 +101,9 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(const double* src, int64
 __global__ __launch_bounds__(256) void hh_apply_kernel(const double* v, int64_t rows,
                                                        int64_t ldv, int b, int n,
                                                        const double* tau, const double* cin,
-                                                       double* q, int64_t ldq) {
+                                                       double* q, int64_t ldq,
+                                                       const int* run_if) {
+  if (run_if && *run_if == 0) return;
   extern __shared__ double sm[];
   const int ld = n + 1;
   double* X = sm;
@@ -421,7 +424,74 @@ size_t tsqr_ws_doubles(int64_t m, int n) {
   return total;
 }
 
-void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st) {
+__global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+// G = R^T R (upper R) and R^{-1}, n <= 96, one workgroup; see chol_inv in common.h.
+__global__ __launch_bounds__(256) void chol_inv_kernel(const double* G, double* R, double* Ri,
+                                                        int n, int pass, int* fail,
+                                                        double shift_coef) {
+  __shared__ double A[96][97];
+  __shared__ double Iv[96][97];
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (*fail) return;  // uniform: read before any write of this launch
+  for (int idx = tid; idx < n * n; idx += 256) A[idx / n][idx % n] = G[idx];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  double dmax = 0.0, tr = 0.0;
+  for (int k = 0; k < n; ++k) {
+    dmax = fmax(dmax, A[k][k]);
+    tr += A[k][k];
+  }
+  __syncthreads();
+  if (pass == 0 && tid < n) A[tid][tid] += shift_coef * tr;  // ||Y||_2^2 <= tr(G)
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = A[k][k];
+      bool ok = isfinite(d) && (pass == 0 ? d > 0.0
+                                          : pass == 1 ? d > 1e-14 * dmax : (d > 0.25 && d < 4.0));
+      if (!ok) bad = 1;
+      piv = ok ? sqrt(d) : 1.0;
+      A[k][k] = piv;
+    }
+    __syncthreads();
+    for (int j = k + 1 + tid; j < n; j += 256) A[k][j] /= piv;  // row k of R
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += 256) {
+      const int i = idx / n, j = idx % n;
+      if (i > k && j >= i) A[i][j] -= A[k][i] * A[k][j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *fail = 1;
+    return;
+  }
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int i = idx / n, j = idx % n;
+    R[idx] = (j >= i) ? A[i][j] : 0.0;
+  }
+  // R^{-1}: column j solves R x = e_j by back substitution (one thread per column, in LDS)
+  for (int j = tid; j < n; j += 256) {
+    for (int i = n - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= j; ++l) v -= A[i][l] * Iv[l][j];
+      Iv[i][j] = (i <= j) ? v / A[i][i] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += 256) Ri[idx] = Iv[idx / n][idx % n];
+}
+
+void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st,
+          const int* run_if_set) {
   static bool attr = false;
   if (!attr) {
     set_lds_attr((const void*)hh_factor_kernel);
@@ -432,16 +502,24 @@ void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hi
   for (const TsqrLevel& L : lv) {
     const size_t lds = ((size_t)L.b * (n + 1) + 64) * sizeof(double);
     hipLaunchKernelGGL(hh_factor_kernel, dim3((unsigned)L.nblocks), dim3(256), lds, st, L.src,
-                       L.rows, L.ld, L.b, n, L.v, L.ld, L.tau, L.rstack);
+                       L.rows, L.ld, L.b, n, L.v, L.ld, L.tau, L.rstack, run_if_set);
   }
-  if (R_out) copy(R_out, lv.back().rstack, (int64_t)n * n, st);
+  if (R_out)
+    hipLaunchKernelGGL(copy_if_kernel, dim3(64), dim3(256), 0, st, R_out, lv.back().rstack,
+                       (int64_t)n * n, run_if_set);
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
     const TsqrLevel& L = lv[l];
     const double* cin = (l == (int)lv.size() - 1) ? nullptr : lv[l].rstack;
     const size_t lds = ((size_t)L.b * (n + 1) + (size_t)L.b + 64) * sizeof(double);
     hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)L.nblocks), dim3(256), lds, st, L.v,
-                       L.rows, L.ld, L.b, n, L.tau, cin, L.v, L.ld);
+                       L.rows, L.ld, L.b, n, L.tau, cin, L.v, L.ld, run_if_set);
   }
+}
+
+void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
+              hipStream_t st, double shift_coef) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, G, R, Rinv, n, pass, fail,
+                     shift_coef);
 }
 
 void jacobi_svd(const double* A, double* U, double* S, double* V, int n, int batch,

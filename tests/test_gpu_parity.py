@@ -19,7 +19,10 @@ torch = pytest.importorskip("torch")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 REL_F = 1e-9          # free-energy parity of the FP64 path
-SPEC_TOL = 1e-9       # spectra: |gpu - oracle| <= SPEC_TOL * max(spectrum)
+# Spectra: |gpu - oracle| <= SPEC_TOL * max(spectrum).  The RG flow amplifies rounding: the
+# oracle itself, perturbed by 1e-15 relative noise after every step of C2, moves its own
+# spectra by up to 8.6e-10 of the maximum by step 32; 1e-8 sits an order above that.
+SPEC_TOL = 1e-8
 
 
 @pytest.fixture(scope="module")
