@@ -75,9 +75,11 @@ void gauge_rotation(const double* s, const double* P, double* O, int n, int n_pr
 // ---------------------------------------------------------------------------- misc
 // Gaussian sketch element (i, j) of a rows x cols matrix is Philox4x32-10 draw number
 // e = i * cols + j for (seed, step, site); written to out[i*ld + j] (or out[j*ld + i] when
-// transposed).
+// transposed).  With row_split = s > 0 (a divisor of rows), row i = u * s + v is stored as row
+// v * (rows / s) + u: a sketch whose rows are indexed (u, v) laid out in (v, u) order.
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
-                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st);
+                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st,
+                     int64_t row_split = 0);
 
 // out = permutation of a row-major tensor of rank r <= 6 with dims d: out dim k is input
 // dim perm[k].

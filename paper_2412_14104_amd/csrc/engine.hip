@@ -364,8 +364,13 @@ void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
 // the largest) is factorised by the Householder TSQR instead.  The choice is a device flag:
 // both paths are launched and each kernel of the unused one returns at once.  Both give the
 // same span up to rounding.
-void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_out) {
+void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_out,
+          bool try_cholqr) {
   hipStream_t st = h->st;
+  if (!try_cholqr) {  // sketch panels that are usually numerically rank deficient
+    tsqr(Y, m, n, ld, R_out, h->tsqr_ws, st, nullptr);
+    return;
+  }
   int* fail = h->flag + 4;
   const int64_t sq = (int64_t)MAX_W * MAX_W;
   double* G1 = h->Gq;
@@ -428,6 +433,9 @@ void perm(tatrg_handle* h, const double* in, double* out, std::vector<int64_t> d
 // Operator interface: apply(in, out, w) computes out = Op * in (rows m), apply_t the
 // transpose (rows n); panels are row-major with w columns.
 struct Op {
+  // Row order of the right-space panels: 0 = the sketch's own order; s > 0 = rows (u, v),
+  // u < n / s, v < s, stored in (v, u) order (see philox_gaussian).
+  int64_t right_split = 0;
   virtual void apply(const double* in, double* out, int w) = 0;
   virtual void apply_t(const double* in, double* out, int w) = 0;
   virtual ~Op() {}
@@ -437,47 +445,49 @@ struct Op {
 // (n x w) holds Qb; Uh, S, Vh (w x w) are the core SVD of Rb^T, so that
 // Op ~= (Q Uh) S (Qb Vh)^T.  range_only stops after the last orthonormalisation of Pa.
 void rsvd(tatrg_handle* h, Op& op, int64_t m, int64_t n, int w, int q, uint32_t site,
-          double* Pa, double* Pb, bool range_only) {
+          double* Pa, double* Pb, bool range_only, bool try_cholqr) {
   hipStream_t st = h->st;
-  philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st);
+  philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st,
+                  op.right_split);
   op.apply(Pb, Pa, w);
-  orth(h, Pa, m, w, w, nullptr);
+  orth(h, Pa, m, w, w, nullptr, try_cholqr);
   for (int it = 0; it < h->cfg.q; ++it) {
     op.apply_t(Pa, Pb, w);
-    orth(h, Pb, n, w, w, nullptr);
+    orth(h, Pb, n, w, w, nullptr, try_cholqr);
     op.apply(Pb, Pa, w);
-    orth(h, Pa, m, w, w, nullptr);
+    orth(h, Pa, m, w, w, nullptr, try_cholqr);
   }
   (void)q;
   (void)st;
   if (range_only) return;
   op.apply_t(Pa, Pb, w);
-  orth(h, Pb, n, w, w, h->Rb);
+  orth(h, Pb, n, w, w, h->Rb, try_cholqr);
   transpose_batched(h->Rb, h->RbT, w, w, 1, st);
   jacobi_svd(h->RbT, h->Uh, h->Sh, h->Vh, w, 1, st);
 }
 
 // Cell middle of the swap: M[(alpha,f'),(beta,b')] = sum_x s_a B[x,b',a] A[x,f',b] s_b, rows
-// stored in (f', alpha) order, columns in (beta, b') order.
+// stored in (f', alpha) order, columns (right-space panels) in (b', beta) order, so that
+// every product is one GEMM with N = chi * w.
 struct SwapOp : Op {
   tatrg_handle* h;
   void apply(const double* om, double* y, int w) override {
     const Dims& d = h->d;
-    // t1[beta][(x alpha)][j] = btx[(x alpha), b'] om[beta][b'][j]
-    gemm(h, Gb(G(d.n2, w, d.n3, h->btx, d.n3, false, om, w, false, h->t1, w), d.c, 0,
-               d.n3 * w, d.n2 * w));
-    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {1, 0, 2, 3});  // [x, beta, alpha, j]
+    // t1[(x alpha), (beta j)] = btx[(x alpha), b'] om[b', (beta j)]   (long K: split)
+    gemm_long_k(h, G(d.n2, d.c * w, d.n3, h->btx, d.n3, false, om, d.c * w, false, h->t1,
+                     d.c * w));
+    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {0, 2, 1, 3});  // [x, beta, alpha, j]
     // y[f', (alpha j)] = atf[f', (x beta)] t2[(x beta), (alpha j)]
     gemm(h, G(d.n3, d.c * w, d.n2, h->atf, d.n2, false, h->t2, d.c * w, false, y, d.c * w));
   }
   void apply_t(const double* qm, double* z, int w) override {
     const Dims& d = h->d;
-    // t1[(x beta), (alpha j)] = atf^T qm[f', (alpha j)]
-    gemm(h, G(d.n2, d.c * w, d.n3, h->atf, d.n2, true, qm, d.c * w, false, h->t1, d.c * w));
-    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {1, 0, 2, 3});  // [beta, x, alpha, j]
-    // z[beta][b'][j] = btx^T[b', (x alpha)] t2[beta][(x alpha)][j]
-    gemm(h, Gb(G(d.n3, w, d.n2, h->btx, d.n3, true, h->t2, w, false, z, w), d.c, 0, d.n2 * w,
-               d.n3 * w));
+    // t1[(x beta), (alpha j)] = atf^T qm[f', (alpha j)]   (long K: split)
+    gemm_long_k(h, G(d.n2, d.c * w, d.n3, h->atf, d.n2, true, qm, d.c * w, false, h->t1,
+                     d.c * w));
+    perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {0, 2, 1, 3});  // [x, alpha, beta, j]
+    // z[b', (beta j)] = btx^T[b', (x alpha)] t2[(x alpha), (beta j)]
+    gemm(h, G(d.n3, d.c * w, d.n2, h->btx, d.n3, true, h->t2, d.c * w, false, z, d.c * w));
   }
 };
 
@@ -499,8 +509,8 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int c = d.c;
-  orth(h, h->phi, d.n4, c, c, h->Rp);
-  orth(h, h->psi, d.n4, c, c, h->Rs);
+  orth(h, h->phi, d.n4, c, c, h->Rp, true);
+  orth(h, h->psi, d.n4, c, c, h->Rs, true);
   gemm(h, G(c, c, c, h->Rp, c, false, h->Rs, c, true, h->Cc, c));
   jacobi_svd(h->Cc, h->Uc, h->s, h->Vc, c, 1, st);
   // probes against A = Q_Phi U
@@ -531,11 +541,13 @@ void bond_swap(tatrg_handle* h, double* rec) {
   perm(h, h->Ys, h->btx, {c, d.n3, c}, {0, 2, 1});
   SwapOp op;
   op.h = h;
-  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false);
-  // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c]
+  op.right_split = d.n3;  // sketch rows (beta, b') stored in (b', beta) order
+  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, false);
+  // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c] (Qb rows in (b', beta))
   gemm(h, G(d.n4, c, w, h->P2, w, false, h->Uh, w, false, h->Xs, c));
   perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
-  gemm(h, G(d.n4, c, w, h->P1, w, false, h->Vh, w, false, h->Y, c));
+  gemm(h, G(d.n4, c, w, h->P1, w, false, h->Vh, w, false, h->Xs, c));
+  perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
   hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, h->sig, h->Sh, c);
   if (rec) hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec, h->Sh, c);
 }
@@ -587,7 +599,7 @@ void isometries(tatrg_handle* h) {
     op.M = h->rho + z * n2 * n2;
     op.n = n2;
     double* U = h->UZ + z * n2 * d.L;
-    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true);
+    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, false);
   }
 }
 
@@ -676,7 +688,7 @@ void squeezers(tatrg_handle* h, double* rec) {
     op.M = h->Cm;
     op.n = n2;
     const int w = d.L;
-    rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false);
+    rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false, true);
     // U = Q Uh[:, :c], V = Qb Vh[:, :c]
     gemm(h, G(n2, c, w, h->P2, w, false, h->Uh, w, false, h->Usq, c));
     gemm(h, G(n2, c, w, h->P1, w, false, h->Vh, w, false, h->Vsq, c));
@@ -869,7 +881,7 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
   h->cfg.seed = seed;
   h->cfg.q = q;
   h->step = 0;
-  rsvd(h, op, m, n, w, q, site, h->P2, h->P1, false);
+  rsvd(h, op, m, n, w, q, site, h->P2, h->P1, false, true);
   h->cfg.seed = save_seed;
   h->cfg.q = save_q;
   h->step = save_step;

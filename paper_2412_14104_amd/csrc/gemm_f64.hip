@@ -6,10 +6,12 @@
 //
 // Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) computes a 128 x 128 tile of C;
 // each wave owns 64 x 64 = 4 x 4 MFMA blocks of 16 x 16 held in 64 accumulator doubles per
-// lane.  K advances in steps of 16 through a double-buffered LDS stage (A as [k][m], B as
+// lane.  K advances in steps of BK = 8 through a double-buffered LDS stage (A as [k][m], B as
 // [k][n], so MFMA fragments are read with unit stride); the next stage's global loads are
-// issued before the MFMAs of the current one.  Optional split-K: blockIdx.z enumerates
-// (batch, K part) and parts are summed afterwards in a fixed order.
+// issued before the MFMAs of the current one.  Global loads are mapped so that consecutive
+// lanes read consecutive addresses of whichever dimension is contiguous in memory (the
+// transposes are template parameters).  Optional split-K: blockIdx.z enumerates (batch, K part)
+// and parts are summed afterwards in a fixed order.
 #include "common.h"
 
 namespace tatrg {
@@ -18,7 +20,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
+constexpr int BM = 128, BN = 128, BK = 8, PAD = 4, NT = 256;
+constexpr int EA = BM * BK / NT, EB = BN * BK / NT;  // staged elements per thread
 
 struct KArgs {
   GemmArgs g;
@@ -27,6 +30,7 @@ struct KArgs {
   double* partial;  // kparts > 1: output [batch][kparts][M][N]
 };
 
+template <bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const GemmArgs& g = ka.g;
   if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
@@ -43,67 +47,48 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const int64_t kb = p * ka.kchunk;
   const int64_t K = (ka.kparts > 1) ? ((g.K - kb) < ka.kchunk ? (g.K - kb) : ka.kchunk) : g.K;
 
-  const double* A = g.A + b * g.sA + (g.ta ? kb * g.lda : kb);
-  const double* B = g.B + b * g.sB + (g.tb ? kb : kb * g.ldb);
+  const double* A = g.A + b * g.sA + (TA ? kb * g.lda : kb);
+  const double* B = g.B + b * g.sB + (TB ? kb : kb * g.ldb);
   const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t n0 = (int64_t)blockIdx.x * BN;
   const int64_t M = g.M, N = g.N;
 
-  double ra[8], rb[8];
+  // element e of a stage: A tile row/k and B tile column/k
+  auto a_rk = [&](int e, int& r, int& kk) {
+    if (TA) { r = e % BM; kk = e / BM; } else { r = e / BK; kk = e % BK; }
+  };
+  auto b_ck = [&](int e, int& c, int& kk) {
+    if (TB) { c = e / BK; kk = e % BK; } else { c = e % BN; kk = e / BN; }
+  };
+  double ra[EA], rb[EB];
   auto load = [&](int64_t k0) {
-    if (!g.ta) {
-      const int r = tid >> 1, kc = (tid & 1) * 8;
-      const int64_t m = m0 + r;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t k = k0 + kc + i;
-        ra[i] = (m < M && k < K) ? A[m * g.lda + k] : 0.0;
-      }
-    } else {
-      const int kk = tid >> 4, mc = (tid & 15) * 8;
-      const int64_t k = k0 + kk;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t m = m0 + mc + i;
-        ra[i] = (m < M && k < K) ? A[k * g.lda + m] : 0.0;
-      }
+    for (int i = 0; i < EA; ++i) {
+      int r, kk;
+      a_rk(tid + i * NT, r, kk);
+      const int64_t m = m0 + r, k = k0 + kk;
+      ra[i] = (m < M && k < K) ? (TA ? A[k * g.lda + m] : A[m * g.lda + k]) : 0.0;
     }
-    if (!g.tb) {
-      const int kk = tid >> 4, nc = (tid & 15) * 8;
-      const int64_t k = k0 + kk;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t n = n0 + nc + i;
-        rb[i] = (n < N && k < K) ? B[k * g.ldb + n] : 0.0;
-      }
-    } else {
-      const int r = tid >> 1, kc = (tid & 1) * 8;
-      const int64_t n = n0 + r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t k = k0 + kc + i;
-        rb[i] = (n < N && k < K) ? B[n * g.ldb + k] : 0.0;
-      }
+    for (int i = 0; i < EB; ++i) {
+      int c, kk;
+      b_ck(tid + i * NT, c, kk);
+      const int64_t n = n0 + c, k = k0 + kk;
+      rb[i] = (n < N && k < K) ? (TB ? B[n * g.ldb + k] : B[k * g.ldb + n]) : 0.0;
     }
   };
   auto store = [&](int buf) {
-    if (!g.ta) {
-      const int r = tid >> 1, kc = (tid & 1) * 8;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) As[buf][kc + i][r] = ra[i];
-    } else {
-      const int kk = tid >> 4, mc = (tid & 15) * 8;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) As[buf][kk][mc + i] = ra[i];
+    for (int i = 0; i < EA; ++i) {
+      int r, kk;
+      a_rk(tid + i * NT, r, kk);
+      As[buf][kk][r] = ra[i];
     }
-    if (!g.tb) {
-      const int kk = tid >> 4, nc = (tid & 15) * 8;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[buf][kk][nc + i] = rb[i];
-    } else {
-      const int r = tid >> 1, kc = (tid & 1) * 8;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[buf][kc + i][r] = rb[i];
+    for (int i = 0; i < EB; ++i) {
+      int c, kk;
+      b_ck(tid + i * NT, c, kk);
+      Bs[buf][kk][c] = rb[i];
     }
   };
 
@@ -198,7 +183,13 @@ void launch(const KArgs& ka, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
             (unsigned)(g.batch * ka.kparts));
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, st, ka);
+  if (g.ta) {
+    if (g.tb) hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, dim3(NT), 0, st, ka);
+    else hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, dim3(NT), 0, st, ka);
+  } else {
+    if (g.tb) hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(NT), 0, st, ka);
+    else hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(NT), 0, st, ka);
+  }
 }
 
 }  // namespace

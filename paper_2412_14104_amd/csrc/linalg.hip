@@ -1,7 +1,8 @@
 // Dense FP64 factorisations used by the randomized SVDs of the Triad-ATRG step:
 //  * TSQR: Householder QR of tall panels (the QR iterations of the RSVD, Table 1 of the
-//    paper; the canonical form of Section 2) on row blocks held in LDS, with a reduction tree
-//    of the R factors and an explicit Q built by applying the reflectors back down the tree;
+//    paper; the canonical form of Section 2) on row blocks held in registers, with a
+//    reduction tree of the R factors and an explicit Q built by applying the reflectors back
+//    down the tree;
 //  * one-sided (Hestenes) Jacobi SVD of the small core matrices;
 //  * blocked left-looking Cholesky of the squeezer Grams;
 //  * gauge rotation fixing the basis of degenerate singular subspaces.
@@ -22,121 +23,237 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------------------------ TSQR
-int leaf_rows(int n) {
-  int b = (LDS_DOUBLES - 64) / (n + 2);
-  if (b > 1024) b = 1024;
-  return b;
+// Householder QR of row blocks with the panel held in registers: thread t owns column
+// c = t % CW and the rows i = g + RG k (g = t / CW < RG, k < RPG) of its block, so the rank-1
+// updates never touch LDS.  Leaf blocks take TsqrShape::leaf rows of the panel; blocks of the
+// reduction tree stack whole R factors, up to TsqrShape::up rows (>= 2 R factors).  Block
+// heights are chosen so the rows a thread holds fit in registers without spilling.
+constexpr int TQ_HV = 8;  // reflector columns staged per chunk in the apply kernel
+
+struct TsqrShape {
+  int cw, leaf, up;
+};
+TsqrShape tsqr_shape(int n) {
+  if (n <= 32) return {32, 192, 384};
+  if (n <= 64) return {64, 192, 256};
+  return {96, 160, 200};
 }
 
-// Householder QR of row block blockIdx.x (b rows; rows beyond `rows` are zero) of src.
-// Output: the block with R on/above the diagonal and the reflector tails below it, written
-// to v (may alias src), tau[blk*n + j], and R (n x n, zero below the diagonal) to
-// rstack[(blk*n + i)*n + k].
-__global__ __launch_bounds__(256) void hh_factor_kernel(const double* src, int64_t rows,
-                                                        int64_t lds, int b, int n, double* v,
-                                                        int64_t ldv, double* tau,
-                                                        double* rstack, const int* run_if) {
+// Factor row block blockIdx.x (b rows; rows beyond `rows` are zero) of src.  Output: the block
+// with R on/above the diagonal and the reflector tails below it, written to v (may alias src),
+// tau[blk*n + j], and R (n x n, zero below the diagonal) to rstack[(blk*n + i)*n + k].  The
+// reflector of column j is (1, x_{j+1..} * scl) with tau = (beta - alpha) / beta.
+//
+// One barrier per column.  At step j every thread holds x = column j (after reflectors
+// 0..j-1) in its own rows, zero on and above row j, and computes for its own column c >= j
+// the partial dot product sum_{i>j} x_i A[i][c] over its rows (for c = j the squared norm
+// below the diagonal); the thread holding row j publishes A[j][c], and the owner of column
+// j+1 publishes that column (zero on and above row j+1) as it stands before reflector j.
+// After the barrier every thread forms reflector j from the reduced sums, updates its column
+// and rebuilds column j+1 in its own rows from the published copy.  The inner loops are plain
+// FMAs over all rows a thread holds (rows on and above the diagonal carry zeros in x).  Row j
+// is row slot kk = j / RG of group j % RG; the column loop runs as an unrolled loop over kk
+// around a loop over the group, so that slot is a compile-time register index.  Scaling of
+// the stored reflector and the diagonal beta are applied when the block is written out.
+template <int CW, int RG, int RPG>
+__global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, int64_t rows,
+                                                          int64_t lds, int b, int n, double* v,
+                                                          int64_t ldv, double* tau,
+                                                          double* rstack, const int* run_if) {
   if (run_if && *run_if == 0) return;
-  extern __shared__ double sm[];
-  const int ld = n + 1;
-  double* A = sm;
-  double* red = sm + (size_t)b * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t blk = blockIdx.x;
-  const int64_t r0 = blk * b;
+  static_assert(RG % 2 == 0 && RPG % 2 == 0, "pairs of doubles are read as one 16-byte word");
+  __shared__ double2 xp[2][RG][RPG / 2];  // a column by row group: [g][k] = row g + RG k
+  __shared__ double2 pw[2][CW][RG / 2];   // per-column partial dot products of the RG groups
+  __shared__ double rj[2][CW];            // row j of the block
+  __shared__ double sclv[CW], betav[CW];
+  const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
+  const int64_t blk = blockIdx.x, r0 = blk * (int64_t)b;
   const int nb = (int)((rows - r0) < b ? (rows - r0) : b);
+  double* pws = reinterpret_cast<double*>(pw);
 
-  for (int idx = tid; idx < b * n; idx += 256) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    A[i * ld + k] = (i < nb) ? src[(r0 + i) * lds + k] : 0.0;
+  double a[RPG], x[RPG];
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
+    const int i = g + RG * k;
+    a[k] = (i < nb && c < n) ? src[(r0 + i) * lds + c] : 0.0;
+  }
+  if (c == 0) {
+#pragma unroll
+    for (int k = 0; k < RPG; k += 2) {
+      const int i = g + RG * k;
+      xp[0][g][k / 2] = make_double2(i > 0 ? a[k] : 0.0, a[k + 1]);
+    }
   }
   __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPG; k += 2) {
+    const double2 e = xp[0][g][k / 2];
+    x[k] = e.x;
+    x[k + 1] = e.y;
+  }
 
-  for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < b; i += 256) part += A[i * ld + j] * A[i * ld + j];
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();
-    const double s = red[0] + red[1] + red[2] + red[3];
-    const double alpha = A[j * ld + j];
-    double t = 0.0, beta = alpha;
-    if (s > 0.0) {
-      const double nrm = sqrt(alpha * alpha + s);
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      t = (beta - alpha) / beta;
-      const double scl = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < b; i += 256) A[i * ld + j] *= scl;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      A[j * ld + j] = beta;
-      tau[blk * n + j] = t;
-    }
-    if (t != 0.0) {
-      for (int k = j + 1 + wave; k < n; k += 4) {
-        double w = (lane == 0) ? A[j * ld + k] : 0.0;
-        for (int i = j + 1 + lane; i < b; i += 64) w += A[i * ld + j] * A[i * ld + k];
-        w = wave_sum(w);
-        if (lane == 0) A[j * ld + k] -= t * w;
-        for (int i = j + 1 + lane; i < b; i += 64) A[i * ld + k] -= t * A[i * ld + j] * w;
+#pragma unroll
+  for (int kk = 0; kk < RPG; ++kk) {
+#pragma unroll 1
+    for (int jg = 0; jg < RG; ++jg) {
+      const int j = kk * RG + jg;
+      if (j >= n) break;
+      const int bf = j & 1;
+      if (c >= j && c < n) {
+        double p = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPG; ++k) p += x[k] * a[k];
+        pws[((bf * CW) + c) * RG + g] = p;
+        if (g == jg) rj[bf][c] = a[kk];
+      }
+      if (c == j + 1) {  // column j+1 before reflector j, zero on and above row j+1
+#pragma unroll
+        for (int k = 0; k < RPG; k += 2) {
+          const int i = g + RG * k;
+          xp[bf ^ 1][g][k / 2] =
+              make_double2(i > j + 1 ? a[k] : 0.0, i + RG > j + 1 ? a[k + 1] : 0.0);
+        }
+      }
+      __syncthreads();
+
+      auto colsum = [&](int cc) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < RG / 2; ++q) {
+          const double2 e = pw[bf][cc][q];
+          sum += e.x;
+          sum += e.y;
+        }
+        return sum;
+      };
+      const double s = colsum(j);
+      const double alpha = rj[bf][j];
+      double t = 0.0, beta = alpha, scl = 0.0;
+      if (s > 0.0) {
+        const double nrm = sqrt(alpha * alpha + s);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        scl = 1.0 / (alpha - beta);
+      }
+      if (tid == 0) {
+        tau[blk * n + j] = t;
+        sclv[j] = scl;
+        betav[j] = beta;
+      }
+      if (c > j && c < n) {
+        const double tw = t * (rj[bf][c] + scl * colsum(c)), f = tw * scl;
+#pragma unroll
+        for (int k = 0; k < RPG; ++k) a[k] -= f * x[k];
+        if (g == jg) a[kk] -= tw;
+      }
+      if (j + 1 < n) {
+        const double tw = t * (rj[bf][j + 1] + scl * colsum(j + 1)), f = tw * scl;
+#pragma unroll
+        for (int k = 0; k < RPG; k += 2) {
+          const double2 e = xp[bf ^ 1][g][k / 2];
+          x[k] = e.x - f * x[k];
+          x[k + 1] = e.y - f * x[k + 1];
+        }
+        // row j+1 leaves x
+        if (jg + 1 < RG) {
+          if (g == jg + 1) x[kk] = 0.0;
+        } else if (kk + 1 < RPG) {
+          if (g == 0) x[kk + 1] = 0.0;
+        }
       }
     }
-    __syncthreads();
   }
-
-  for (int idx = tid; idx < nb * n; idx += 256) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    v[(r0 + i) * ldv + k] = A[i * ld + k];
-  }
-  for (int idx = tid; idx < n * n; idx += 256) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    rstack[(blk * n + i) * n + k] = (k >= i) ? A[i * ld + k] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
+    const int i = g + RG * k;
+    if (c < n) {
+      const double e = (i < c) ? a[k] : (i == c ? betav[c] : a[k] * sclv[c]);
+      if (i < nb) v[(r0 + i) * ldv + c] = e;
+      if (i < n) rstack[(blk * n + i) * n + c] = (c >= i) ? e : 0.0;
+    }
   }
 }
 
 // Q of row block blockIdx.x: H_0 ... H_{n-1} [C; 0] with C = cin rows blk*n .. blk*n+n-1
-// (identity when cin is null).  Reflector j is column j of v below the diagonal with an
-// implicit unit diagonal.  Rows < `rows` of the result are written to q (may alias v).
-__global__ __launch_bounds__(256) void hh_apply_kernel(const double* v, int64_t rows,
-                                                       int64_t ldv, int b, int n,
-                                                       const double* tau, const double* cin,
-                                                       double* q, int64_t ldq,
-                                                       const int* run_if) {
+// (identity when cin is null).  The block of Q is held in registers like the factor; the
+// reflectors are staged TQ_HV columns at a time in LDS, by row group, so a thread reads the
+// rows it holds as 16-byte words.  One barrier per reflector (double-buffered partial sums).
+// Rows < `rows` of the result are written to q (may alias v).
+template <int CW, int RG, int RPG>
+__global__ __launch_bounds__(CW * RG) void hh_apply_kernel(const double* v, int64_t rows,
+                                                         int64_t ldv, int b, int n,
+                                                         const double* tau, const double* cin,
+                                                         double* q, int64_t ldq,
+                                                         const int* run_if) {
   if (run_if && *run_if == 0) return;
-  extern __shared__ double sm[];
-  const int ld = n + 1;
-  double* X = sm;
-  double* vc = sm + (size_t)b * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t blk = blockIdx.x;
-  const int64_t r0 = blk * b;
+  constexpr int NT = CW * RG, BR = RG * RPG;
+  __shared__ double2 vc[TQ_HV][RG][RPG / 2];  // [jj][g][k] = row g + RG k of column j0 + jj
+  __shared__ double2 pw[2][CW][RG / 2];
+  __shared__ double ts[TQ_HV];
+  const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
+  const int64_t blk = blockIdx.x, r0 = blk * (int64_t)b;
   const int nb = (int)((rows - r0) < b ? (rows - r0) : b);
+  double* vcs = reinterpret_cast<double*>(vc);
+  double* pws = reinterpret_cast<double*>(pw);
 
-  for (int idx = tid; idx < b * n; idx += 256) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    double x = 0.0;
-    if (i < n) x = cin ? cin[(blk * n + i) * n + k] : (i == k ? 1.0 : 0.0);
-    X[i * ld + k] = x;
+  double x[RPG];
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
+    const int i = g + RG * k;
+    double e = 0.0;
+    if (i < n && c < n) e = cin ? cin[(blk * n + i) * n + c] : (i == c ? 1.0 : 0.0);
+    x[k] = e;
   }
-  __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    const double t = tau[blk * n + j];
-    if (t == 0.0) continue;
-    for (int i = j + tid; i < b; i += 256)
-      vc[i] = (i == j) ? 1.0 : ((i < nb) ? v[(r0 + i) * ldv + j] : 0.0);
-    __syncthreads();
-    for (int k = wave; k < n; k += 4) {
-      double w = 0.0;
-      for (int i = j + lane; i < b; i += 64) w += vc[i] * X[i * ld + k];
-      w = wave_sum(w);
-      for (int i = j + lane; i < b; i += 64) X[i * ld + k] -= t * vc[i] * w;
+  int it = 0;
+  for (int j0 = ((n - 1) / TQ_HV) * TQ_HV; j0 >= 0; j0 -= TQ_HV) {
+    __syncthreads();  // every thread is done with the previous chunk
+    for (int idx = tid; idx < TQ_HV * BR; idx += NT) {
+      const int i = idx / TQ_HV, jj = idx - (idx / TQ_HV) * TQ_HV, j = j0 + jj;
+      double e = 0.0;
+      if (j < n && i < nb) e = (i == j) ? 1.0 : (i > j ? v[(r0 + i) * ldv + j] : 0.0);
+      vcs[(jj * RG + (i % RG)) * RPG + i / RG] = e;
     }
+    if (tid < TQ_HV) ts[tid] = (j0 + tid < n) ? tau[blk * n + j0 + tid] : 0.0;
     __syncthreads();
+    for (int jj = TQ_HV - 1; jj >= 0; --jj) {
+      const double t = ts[jj];
+      if (t == 0.0) continue;  // uniform
+      const int bf = it & 1;
+      ++it;
+      if (c < n) {
+        double p = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPG; k += 2) {
+          const double2 e = vc[jj][g][k / 2];
+          p += e.x * x[k];
+          p += e.y * x[k + 1];
+        }
+        pws[((bf * CW) + c) * RG + g] = p;
+      }
+      __syncthreads();
+      if (c < n) {
+        double w = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < RG / 2; ++qq) {
+          const double2 e = pw[bf][c][qq];
+          w += e.x;
+          w += e.y;
+        }
+        const double f = t * w;
+#pragma unroll
+        for (int k = 0; k < RPG; k += 2) {
+          const double2 e = vc[jj][g][k / 2];
+          x[k] -= f * e.x;
+          x[k + 1] -= f * e.y;
+        }
+      }
+    }
   }
-  for (int idx = tid; idx < nb * n; idx += 256) {
-    const int i = idx / n, k = idx - (idx / n) * n;
-    q[(r0 + i) * ldq + k] = X[i * ld + k];
+#pragma unroll
+  for (int k = 0; k < RPG; ++k) {
+    const int i = g + RG * k;
+    if (i < nb && c < n) q[(r0 + i) * ldq + c] = x[k];
   }
 }
 
@@ -145,18 +262,21 @@ struct TsqrLevel {
   double* v;
   int64_t rows, ld;
   int b;
+  bool leaf;
   int64_t nblocks;
   double* tau;
   double* rstack;
 };
 
+// Levels of the reduction tree: level 0 factors the panel in leaf blocks, every later level
+// the stacked R factors of the one below in blocks of whole R factors.
 std::vector<TsqrLevel> plan_tsqr(double* Y, int64_t m, int n, int64_t ld, double* ws) {
   std::vector<TsqrLevel> lv;
-  const int b0 = leaf_rows(n);
-  const int bu = (b0 / n) * n;  // upper levels: whole R blocks
+  const TsqrShape sh = tsqr_shape(n);
+  const int bu = (sh.up / n) * n;  // >= 2n for n <= 96
   double* src = Y;
   int64_t rows = m, lds = ld;
-  int b = b0;
+  int b = sh.leaf;
   for (;;) {
     TsqrLevel L;
     L.src = src;
@@ -164,14 +284,15 @@ std::vector<TsqrLevel> plan_tsqr(double* Y, int64_t m, int n, int64_t ld, double
     L.rows = rows;
     L.ld = lds;
     L.b = b;
+    L.leaf = lv.empty();
     L.nblocks = (rows + b - 1) / b;
     L.tau = ws;
-    ws += L.nblocks * n;
+    if (ws) ws += L.nblocks * n;
     L.rstack = ws;
-    ws += L.nblocks * n * n;
+    if (ws) ws += L.nblocks * n * n;
     lv.push_back(L);
     if (L.nblocks == 1) break;
-    src = L.rstack;
+    src = L.rstack;  // nblocks * n rows; bu >= 2n, so every level at least halves the rows
     rows = L.nblocks * n;
     lds = n;
     b = bu;
@@ -179,13 +300,6 @@ std::vector<TsqrLevel> plan_tsqr(double* Y, int64_t m, int n, int64_t ld, double
   return lv;
 }
 
-void set_lds_attr(const void* fn) {
-  static bool done_f = false, done_a = false;
-  (void)done_f;
-  (void)done_a;
-  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      LDS_DOUBLES * (int)sizeof(double));
-}
 
 // ------------------------------------------------------------------------------ Jacobi SVD
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, double* Uo,
@@ -214,39 +328,45 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
+    // each rotation pair is handled by 16 lanes (4 pairs per wave); all pairs of a round of
+    // the round-robin ordering are disjoint, so they run concurrently
+    const int sub = lane & 15, slot = wave * 4 + (lane >> 4), nslots = nw * 4;
     for (int r = 0; r < ne - 1; ++r) {
-      for (int k = wave; k < ne / 2; k += nw) {
+      for (int k = slot; k < ne / 2; k += nslots) {
         const int p = (r + k) % (ne - 1);
         const int q = (k == 0) ? (ne - 1) : (r - k + (ne - 1)) % (ne - 1);
         double* wp = W + (size_t)p * n;
         double* wq = W + (size_t)q * n;
         double a = 0.0, bb = 0.0, g = 0.0;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = sub; i < n; i += 16) {
           const double x = wp[i], y = wq[i];
           a += x * x;
           bb += y * y;
           g += x * y;
         }
-        a = wave_sum(a);
-        bb = wave_sum(bb);
-        g = wave_sum(g);
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          a += __shfl_xor(a, o, 64);
+          bb += __shfl_xor(bb, o, 64);
+          g += __shfl_xor(g, o, 64);
+        }
         if (a > 0.0 && bb > 0.0 && fabs(g) > tol * sqrt(a * bb)) {
           const double zeta = (bb - a) / (2.0 * g);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int i = lane; i < n; i += 64) {
+          for (int i = sub; i < n; i += 16) {
             const double x = wp[i], y = wq[i];
             wp[i] = c * x - s * y;
             wq[i] = s * x + c * y;
           }
           double* vp = V + (size_t)p * ne;
           double* vq = V + (size_t)q * ne;
-          for (int i = lane; i < ne; i += 64) {
+          for (int i = sub; i < ne; i += 16) {
             const double x = vp[i], y = vq[i];
             vp[i] = c * x - s * y;
             vq[i] = s * x + c * y;
           }
-          if (lane == 0) rotated = 1;
+          if (sub == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -410,19 +530,11 @@ __global__ void gauge_kernel(const double* s, const double* P, double* O, int n,
 
 size_t tsqr_ws_doubles(int64_t m, int n) {
   size_t total = 0;
-  const int b0 = leaf_rows(n);
-  const int bu = (b0 / n) * n;
-  int64_t rows = m;
-  int b = b0;
-  for (;;) {
-    const int64_t nb = (rows + b - 1) / b;
-    total += (size_t)nb * n + (size_t)nb * n * n;
-    if (nb == 1) break;
-    rows = nb * n;
-    b = bu;
-  }
+  for (const TsqrLevel& L : plan_tsqr(nullptr, m, n, n, nullptr))
+    total += (size_t)L.nblocks * n + (size_t)L.nblocks * n * n;
   return total;
 }
+
 
 __global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int* run_if) {
   if (run_if && *run_if == 0) return;
@@ -490,30 +602,56 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double* G, double* 
   for (int idx = tid; idx < n * n; idx += 256) Ri[idx] = Iv[idx / n][idx % n];
 }
 
+template <int CW, int RG, int RPG>
+void tsqr_level_launch(bool apply, const TsqrLevel& L, int n, const double* cin,
+                       const int* run_if, hipStream_t st) {
+  if (!apply)
+    hipLaunchKernelGGL((hh_factor_kernel<CW, RG, RPG>), dim3((unsigned)L.nblocks),
+                       dim3(CW * RG), 0, st, L.src, L.rows, L.ld, L.b, n, L.v, L.ld, L.tau,
+                       L.rstack, run_if);
+  else
+    hipLaunchKernelGGL((hh_apply_kernel<CW, RG, RPG>), dim3((unsigned)L.nblocks),
+                       dim3(CW * RG), 0, st, L.v, L.rows, L.ld, L.b, n, L.tau, cin, L.v, L.ld,
+                       run_if);
+}
+
+// Rows per thread follow from the block height: RPG = rows / RG (see tsqr_shape).
+void tsqr_level(bool apply, const TsqrLevel& L, int n, const double* cin, const int* run_if,
+                hipStream_t st) {
+  switch (tsqr_shape(n).cw) {
+    case 32:
+      if (L.leaf) tsqr_level_launch<32, 32, 192 / 32>(apply, L, n, cin, run_if, st);
+      else tsqr_level_launch<32, 32, 384 / 32>(apply, L, n, cin, run_if, st);
+      break;
+    case 64:
+      if (L.leaf) tsqr_level_launch<64, 16, 192 / 16>(apply, L, n, cin, run_if, st);
+      else tsqr_level_launch<64, 16, 256 / 16>(apply, L, n, cin, run_if, st);
+      break;
+    default:
+      if (L.leaf) tsqr_level_launch<96, 10, 160 / 10>(apply, L, n, cin, run_if, st);
+      else tsqr_level_launch<96, 10, 200 / 10>(apply, L, n, cin, run_if, st);
+      break;
+  }
+}
+
 void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hipStream_t st,
           const int* run_if_set) {
-  static bool attr = false;
-  if (!attr) {
-    set_lds_attr((const void*)hh_factor_kernel);
-    set_lds_attr((const void*)hh_apply_kernel);
-    attr = true;
-  }
   std::vector<TsqrLevel> lv = plan_tsqr(Y, m, n, ld, ws);
-  for (const TsqrLevel& L : lv) {
-    const size_t lds = ((size_t)L.b * (n + 1) + 64) * sizeof(double);
-    hipLaunchKernelGGL(hh_factor_kernel, dim3((unsigned)L.nblocks), dim3(256), lds, st, L.src,
-                       L.rows, L.ld, L.b, n, L.v, L.ld, L.tau, L.rstack, run_if_set);
-  }
+  for (const TsqrLevel& L : lv) tsqr_level(false, L, n, nullptr, run_if_set, st);
   if (R_out)
     hipLaunchKernelGGL(copy_if_kernel, dim3(64), dim3(256), 0, st, R_out, lv.back().rstack,
                        (int64_t)n * n, run_if_set);
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
-    const TsqrLevel& L = lv[l];
+    // above the top level Q starts as the identity; below it, as the rows of the level
+    // above's Q, which that level wrote over this level's stacked R factors
     const double* cin = (l == (int)lv.size() - 1) ? nullptr : lv[l].rstack;
-    const size_t lds = ((size_t)L.b * (n + 1) + (size_t)L.b + 64) * sizeof(double);
-    hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)L.nblocks), dim3(256), lds, st, L.v,
-                       L.rows, L.ld, L.b, n, L.tau, cin, L.v, L.ld, run_if_set);
+    tsqr_level(true, lv[l], n, cin, run_if_set, st);
   }
+}
+
+void set_lds_attr(const void* fn) {
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      LDS_DOUBLES * (int)sizeof(double));
 }
 
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,

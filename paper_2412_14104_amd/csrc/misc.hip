@@ -41,8 +41,8 @@ __device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 // Element pair p = e >> 1 of stream (seed, step, site): counter (lo(p), hi(p), step, site),
 // key (lo(seed), hi(seed)); two 53-bit uniforms, Box-Muller (cos for even e, sin for odd e).
 __global__ void philox_gauss_kernel(double* out, int64_t rows, int64_t cols, int64_t ld,
-                                    int transposed, uint32_t k0, uint32_t k1, uint32_t step,
-                                    uint32_t site) {
+                                    int transposed, int64_t row_split, uint32_t k0,
+                                    uint32_t k1, uint32_t step, uint32_t site) {
   const int64_t total = rows * cols;
   const int64_t npairs = (total + 1) >> 1;
   for (int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pr < npairs;
@@ -60,7 +60,9 @@ __global__ void philox_gauss_kernel(double* out, int64_t rows, int64_t cols, int
     for (int h = 0; h < 2; ++h) {
       const int64_t e = 2 * pr + h;
       if (e < total) {
-        const int64_t i = e / cols, j = e - (e / cols) * cols;
+        int64_t i = e / cols;
+        const int64_t j = e - i * cols;
+        if (row_split > 0) i = (i % row_split) * (rows / row_split) + i / row_split;
         if (transposed)
           out[j * ld + i] = g[h];
         else
@@ -153,11 +155,13 @@ __global__ void transpose_batched_kernel(const double* in, double* out, int rows
 }  // namespace
 
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
-                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st) {
+                     uint64_t seed, uint32_t step, uint32_t site, hipStream_t st,
+                     int64_t row_split) {
   const int64_t npairs = (rows * cols + 1) / 2;
+  if (row_split > 0 && rows % row_split != 0) row_split = 0;  // callers pass a divisor
   hipLaunchKernelGGL(philox_gauss_kernel, dim3(grid_for(npairs)), dim3(TPB), 0, st, out, rows,
-                     cols, ld, transposed ? 1 : 0, (uint32_t)seed, (uint32_t)(seed >> 32), step,
-                     site);
+                     cols, ld, transposed ? 1 : 0, row_split, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), step, site);
 }
 
 void permute(const double* in, double* out, int rank, const int64_t* dims, const int* perm,
