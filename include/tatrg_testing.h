@@ -56,6 +56,15 @@ int tatrg_test_svd(const double* A, double* U, double* S, double* V, int n, int 
 int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag,
                         void* stream);
 
+/* Upper Cholesky factor R (G = R^T R) and its inverse of one n x n Gram (n <= 96), the
+ * building block of the CholeskyQR orthonormalisation.  pass 0 factors
+ * G + shift_coef * tr(G) * I and fails only on a non-positive or non-finite pivot; pass 1
+ * fails when a pivot (of L D L^T) is <= 1e-14 of the largest diagonal entry; pass 2 when a
+ * pivot leaves (0.25, 4).  A failure sets *fail = 1 (device int, left untouched otherwise;
+ * nothing is computed when it is already set) and R, Rinv are then not written. */
+int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pass,
+                        double shift_coef, int* fail, void* stream);
+
 /* Gaussian sketch: element (i, j) of a rows x cols matrix is Philox4x32-10 draw number
  * i*cols + j of (seed, step, site). */
 int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,

@@ -343,17 +343,20 @@ void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
   }
 }
 
-// Deterministic split-K for Grams with long K and a small output.
+// Deterministic split-K for products with a small output and a long K: enough parts for
+// about four workgroups per compute unit, at least 128 values of K per part.
 void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
   const int64_t mn = g.M * g.N * g.batch;
-  int parts = (int)std::min<int64_t>(g.K / 1024, (int64_t)(h->partial_doubles / (size_t)mn));
-  if (parts > 256) parts = 256;
   const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  int64_t parts = (1024 + tiles - 1) / tiles;
+  parts = std::min<int64_t>(parts, g.K / 128);
+  parts = std::min<int64_t>(parts, (int64_t)(h->partial_doubles / (size_t)mn));
+  parts = std::min<int64_t>(parts, 2048);
   if (tiles >= 256 || parts < 2) {
     gemm_f64(g, h->st);
     return;
   }
-  gemm_f64_splitk(g, parts, h->partial, h->st);
+  gemm_f64_splitk(g, (int)parts, h->partial, h->st);
 }
 
 // Orthonormal basis of a tall panel Y (m x n, ld), in place: Y <- Q with Y_in = Q R.
@@ -496,10 +499,10 @@ struct DenseOp : Op {
   const double* M;
   int64_t n;
   void apply(const double* in, double* out, int w) override {
-    gemm(h, G(n, w, n, M, n, false, in, w, false, out, w));
+    gemm_long_k(h, G(n, w, n, M, n, false, in, w, false, out, w));
   }
   void apply_t(const double* in, double* out, int w) override {
-    gemm(h, G(n, w, n, M, n, true, in, w, false, out, w));
+    gemm_long_k(h, G(n, w, n, M, n, true, in, w, false, out, w));
   }
 };
 

@@ -30,7 +30,10 @@ struct KArgs {
   double* partial;  // kparts > 1: output [batch][kparts][M][N]
 };
 
-template <bool TA, bool TB>
+// PLAIN: C = op(A) op(B) (alpha = 1, beta = 0, or a split-K partial).  The accumulators are
+// then stored straight from the accumulation registers; the general epilogue (scaling by
+// alpha, adding beta C) moves them to vector registers first and halves the occupancy.
+template <bool TA, bool TB, bool PLAIN>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const GemmArgs& g = ka.g;
   if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
@@ -150,9 +153,13 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
         const int64_t row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
         const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          double val = alpha * acc[i][j][v];
-          if (beta != 0.0) val += beta * C[row * ldc + col];
-          C[row * ldc + col] = val;
+          if (PLAIN) {
+            C[row * ldc + col] = acc[i][j][v];
+          } else {
+            double val = alpha * acc[i][j][v];
+            if (beta != 0.0) val += beta * C[row * ldc + col];
+            C[row * ldc + col] = val;
+          }
         }
       }
 }
@@ -178,17 +185,24 @@ __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64
   }
 }
 
+template <bool TA, bool TB>
+void launch_b(const KArgs& ka, dim3 grid, hipStream_t st) {
+  const bool plain = ka.kparts > 1 || (ka.g.alpha == 1.0 && ka.g.beta == 0.0);
+  if (plain) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true>), grid, dim3(NT), 0, st, ka);
+  else hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false>), grid, dim3(NT), 0, st, ka);
+}
+
 void launch(const KArgs& ka, hipStream_t st) {
   const GemmArgs& g = ka.g;
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
             (unsigned)(g.batch * ka.kparts));
   if (g.ta) {
-    if (g.tb) hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, dim3(NT), 0, st, ka);
-    else hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, dim3(NT), 0, st, ka);
+    if (g.tb) launch_b<true, true>(ka, grid, st);
+    else launch_b<true, false>(ka, grid, st);
   } else {
-    if (g.tb) hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(NT), 0, st, ka);
-    else hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(NT), 0, st, ka);
+    if (g.tb) launch_b<false, true>(ka, grid, st);
+    else launch_b<false, false>(ka, grid, st);
   }
 }
 

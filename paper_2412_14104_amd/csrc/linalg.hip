@@ -544,16 +544,23 @@ __global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int*
 }
 
 // G = R^T R (upper R) and R^{-1}, n <= 96, one workgroup; see chol_inv in common.h.
-__global__ __launch_bounds__(256) void chol_inv_kernel(const double* G, double* R, double* Ri,
-                                                        int n, int pass, int* fail,
-                                                        double shift_coef) {
+// Symmetric elimination on the upper triangle: step k subtracts m_i = A[k][i] / d_k times row
+// k from every row i > k (d_k = A[k][k], the k-th pivot of G = L D L^T).  The same row
+// operations applied to the identity build E = L^{-1}, so R = D^{1/2} L^T and
+// R^{-1} = E^T D^{-1/2} come out of one pass with one barrier per pivot.
+__global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double* R, double* Ri,
+                                                         int n, int pass, int* fail,
+                                                         double shift_coef) {
   __shared__ double A[96][97];
-  __shared__ double Iv[96][97];
-  __shared__ double piv;
+  __shared__ double E[96][97];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (*fail) return;  // uniform: read before any write of this launch
-  for (int idx = tid; idx < n * n; idx += 256) A[idx / n][idx % n] = G[idx];
+  for (int idx = tid; idx < n * n; idx += 1024) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    A[i][j] = G[idx];
+    E[i][j] = (i == j) ? 1.0 : 0.0;
+  }
   if (tid == 0) bad = 0;
   __syncthreads();
   double dmax = 0.0, tr = 0.0;
@@ -565,20 +572,18 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double* G, double* 
   if (pass == 0 && tid < n) A[tid][tid] += shift_coef * tr;  // ||Y||_2^2 <= tr(G)
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = A[k][k];
-      bool ok = isfinite(d) && (pass == 0 ? d > 0.0
-                                          : pass == 1 ? d > 1e-14 * dmax : (d > 0.25 && d < 4.0));
-      if (!ok) bad = 1;
-      piv = ok ? sqrt(d) : 1.0;
-      A[k][k] = piv;
-    }
-    __syncthreads();
-    for (int j = k + 1 + tid; j < n; j += 256) A[k][j] /= piv;  // row k of R
-    __syncthreads();
-    for (int idx = tid; idx < n * n; idx += 256) {
-      const int i = idx / n, j = idx % n;
-      if (i > k && j >= i) A[i][j] -= A[k][i] * A[k][j];
+    const double d = A[k][k];
+    const bool ok = isfinite(d) && (pass == 0 ? d > 0.0
+                                              : pass == 1 ? d > 1e-14 * dmax
+                                                          : (d > 0.25 && d < 4.0));
+    if (!ok && tid == 0) bad = 1;
+    const double rd = 1.0 / (ok ? d : 1.0);
+    const int m = n - k - 1;
+    for (int idx = tid; idx < m * n; idx += 1024) {
+      const int i = k + 1 + idx / n, q = idx - (idx / n) * n;
+      const double mi = A[k][i] * rd;
+      if (q >= i) A[i][q] -= mi * A[k][q];
+      else if (q <= k) E[i][q] -= mi * E[k][q];
     }
     __syncthreads();
   }
@@ -586,20 +591,12 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double* G, double* 
     if (tid == 0) *fail = 1;
     return;
   }
-  for (int idx = tid; idx < n * n; idx += 256) {
-    const int i = idx / n, j = idx % n;
-    R[idx] = (j >= i) ? A[i][j] : 0.0;
+  for (int idx = tid; idx < n * n; idx += 1024) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    const double di = A[i][i], dj = A[j][j];
+    R[idx] = (j > i) ? A[i][j] / sqrt(di) : (j == i ? sqrt(di) : 0.0);
+    Ri[idx] = (j >= i) ? E[j][i] / sqrt(dj) : 0.0;
   }
-  // R^{-1}: column j solves R x = e_j by back substitution (one thread per column, in LDS)
-  for (int j = tid; j < n; j += 256) {
-    for (int i = n - 1; i >= 0; --i) {
-      double v = (i == j) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= j; ++l) v -= A[i][l] * Iv[l][j];
-      Iv[i][j] = (i <= j) ? v / A[i][i] : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += 256) Ri[idx] = Iv[idx / n][idx % n];
 }
 
 template <int CW, int RG, int RPG>
@@ -656,7 +653,7 @@ void set_lds_attr(const void* fn) {
 
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
               hipStream_t st, double shift_coef) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, G, R, Rinv, n, pass, fail,
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, R, Rinv, n, pass, fail,
                      shift_coef);
 }
 

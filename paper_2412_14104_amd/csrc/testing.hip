@@ -83,6 +83,13 @@ int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag
   return launched();
 }
 
+int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pass,
+                        double shift_coef, int* fail, void* stream) {
+  if (!G || !R || !Rinv || !fail || n < 1 || n > 96 || pass < 0 || pass > 2) return -1;
+  chol_inv(G, R, Rinv, n, pass, fail, (hipStream_t)stream, shift_coef);
+  return launched();
+}
+
 int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,
                       uint32_t site, void* stream) {
   if (!out || rows < 1 || cols < 1) return -1;

@@ -200,6 +200,44 @@ def test_cholesky_flags_indefinite_matrix(lib):
     assert host(flag)[0] == 1
 
 
+@pytest.mark.parametrize("n,pass_", [(1, 1), (7, 0), (32, 1), (96, 0), (96, 1), (96, 2)])
+def test_chol_inv_factor_and_inverse(lib, n, pass_):
+    rng = np.random.default_rng(100 * n + pass_)
+    if pass_ == 2:   # near the identity, as in the last CholeskyQR pass
+        e = rng.standard_normal((n, n)) * 1e-3
+        gram = np.eye(n) + e @ e.T
+    else:
+        y = rng.standard_normal((3 * n + 5, n)) * np.logspace(0, -4, n)[None, :]
+        gram = y.T @ y
+    shift = 1e-10 if pass_ == 0 else 0.0
+    dr = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    dri = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    fail = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert lib.tatrg_test_chol_inv(vp(dev(gram)), vp(dr), vp(dri), n, pass_, shift, vp(fail),
+                                   stream()) == 0
+    assert host(fail)[0] == 0
+    r, ri = host(dr), host(dri)
+    ref = gram + shift * np.trace(gram) * np.eye(n)
+    assert np.abs(np.tril(r, -1)).max() == 0.0 and np.abs(np.tril(ri, -1)).max() == 0.0
+    assert np.abs(r.T @ r - ref).max() < 1e-14 * np.abs(ref).max() * n
+    assert np.abs(r - np.linalg.cholesky(ref).T).max() < 1e-10 * np.abs(r).max()
+    assert np.abs(ri @ r - np.eye(n)).max() < 1e-12 * np.linalg.cond(r)
+
+
+def test_chol_inv_flags_a_singular_gram(lib):
+    n = 12
+    y = np.random.default_rng(1).standard_normal((40, n))
+    y[:, 5] = 0.0          # pivot 5 is exactly zero
+    gram = y.T @ y
+    fail = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dr = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    dri = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_chol_inv(vp(dev(gram)), vp(dr), vp(dri), n, 1, 0.0, vp(fail),
+                                   stream()) == 0
+    assert host(fail)[0] == 1
+    assert not host(dr).any()
+
+
 def test_philox_sketch_matches_oracle(lib):
     from oracle import philox
     for (rows, cols, seed, step, site) in [(7, 5, 0, 0, 0), (1000, 96, 0, 39, 0),
