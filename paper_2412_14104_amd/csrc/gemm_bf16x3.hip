@@ -3,9 +3,11 @@
 //
 // Every float64 operand x is split into three bf16 planes x = x0 + x1 + x2 (each residual is
 // formed exactly in float64 before rounding to bf16), so the planes hold ~24 significant
-// bits.  C = sum_{i+j<=2} A_i B_j: six bf16 x bf16 products on v_mfma_f32_16x16x32_bf16,
-// accumulated in float32 within a window of K and added into float64 accumulators at the end
-// of every window, so the float32 rounding grows with the window length only.
+// bits.  C = sum_{i+j<=2} A_i B_j: six bf16 x bf16 products on v_mfma_f32_16x16x32_bf16.  The
+// leading product A_0 B_0 has float32 accumulators of its own that are added into float64
+// accumulators after every 32-wide step of K (one MFMA per block), so its float32 rounding is
+// that of a single 32-term dot product; the five smaller products (2^-8 of its size and less)
+// share a second set flushed every LO_FLUSH_TILES steps.
 //
 // Tiling: 256 threads (4 wave64 in a 2 x 2 grid), 128 x 128 tile of C, 64 x 64 per wave as 4 x 4
 // MFMA blocks; K advances by 32 through double-buffered LDS holding all six planes of the
@@ -21,7 +23,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8, NT = 256;
-constexpr int FLUSH_TILES = 4;   // float32 accumulation window: 4 x 32 = 128 values of K
+constexpr int LO_FLUSH_TILES = 4;  // float32 window of the small products: 4 x 32 values of K
 
 __device__ inline uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -135,13 +137,14 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3_kernel(BArgs ba) {
     }
   };
 
-  f4 acc[4][4];
+  f4 hi[4][4], lo[4][4];
   double dacc[4][4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      hi[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      lo[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int v = 0; v < 4; ++v) dacc[i][j][v] = 0.0;
     }
@@ -171,17 +174,29 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3_kernel(BArgs ba) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          if (pr == 0)
+            hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], hi[i][j], 0, 0, 0);
+          else
+            lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], lo[i][j], 0, 0, 0);
+        }
     }
-    if ((kt + 1) % FLUSH_TILES == 0 || kt + 1 == nk) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[i][j][v] += (double)hi[i][j][v];
+        hi[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    if ((kt + 1) % LO_FLUSH_TILES == 0 || kt + 1 == nk) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) dacc[i][j][v] += (double)acc[i][j][v];
-          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          for (int v = 0; v < 4; ++v) dacc[i][j][v] += (double)lo[i][j][v];
+          lo[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
     if (kt + 1 < nk) store(cur ^ 1);

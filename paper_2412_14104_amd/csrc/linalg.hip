@@ -36,7 +36,7 @@ struct TsqrShape {
 TsqrShape tsqr_shape(int n) {
   if (n <= 32) return {32, 192, 384};
   if (n <= 64) return {64, 192, 256};
-  return {96, 160, 200};
+  return {96, 160, 192};
 }
 
 // Factor row block blockIdx.x (b rows; rows beyond `rows` are zero) of src.  Output: the block
@@ -625,8 +625,8 @@ void tsqr_level(bool apply, const TsqrLevel& L, int n, const double* cin, const 
       else tsqr_level_launch<64, 16, 256 / 16>(apply, L, n, cin, run_if, st);
       break;
     default:
-      if (L.leaf) tsqr_level_launch<96, 10, 160 / 10>(apply, L, n, cin, run_if, st);
-      else tsqr_level_launch<96, 10, 200 / 10>(apply, L, n, cin, run_if, st);
+      if (L.leaf) tsqr_level_launch<96, 8, 160 / 8>(apply, L, n, cin, run_if, st);
+      else tsqr_level_launch<96, 8, 192 / 8>(apply, L, n, cin, run_if, st);
       break;
   }
 }

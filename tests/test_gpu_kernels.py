@@ -70,8 +70,9 @@ def test_gemm_f64_matches_numpy(lib, m, n, k, ta, tb):
 
 @pytest.mark.parametrize("m,n,k,ta,tb", GEMM_CASES[:6] + [(384, 256, 9216, True, False)])
 def test_gemm_bf16x3_is_fp32_class(lib, m, n, k, ta, tb):
-    """Three bf16 planes, six products: |C - AB| ~ (2^-24 per product + fp32 accumulation in
-    windows of 128) * |A||B|; bound 2e-6 * sqrt-free |A||B|."""
+    """Three bf16 planes, six products: |C - AB| is about 2^-24 * |A||B| (the dropped products
+    and the last plane's rounding) plus the float32 rounding of one 32-term dot product per
+    flush of the leading product; bound 3e-7 * |A||B| (measured worst 7e-8)."""
     rng = np.random.default_rng(m + 7 * n + k)
     batch = 2
     a = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
@@ -93,7 +94,8 @@ def test_gemm_bf16x3_is_fp32_class(lib, m, n, k, ta, tb):
         ref = aa @ bb
         scale = np.abs(aa) @ np.abs(bb)
         worst = max(worst, (np.abs(got[i] - ref) / scale).max())
-    assert worst < 2e-6, worst
+    print("split-bf16 GEMM worst |C - AB| / (|A||B|) =", worst, flush=True)
+    assert worst < 3e-7, worst
 
 
 def test_gemm_split_k_is_deterministic_and_correct(lib):
