@@ -27,8 +27,9 @@ void gemm_f64(const GemmArgs& g, hipStream_t st);
 
 // Split-bf16 variant: every operand is split x = x0 + x1 + x2 into bf16 planes and the six
 // products with i + j <= 2 are accumulated in fp32 on the bf16 MFMA units.  Same contract.
+// ev_after_split (optional) is recorded on st between the plane splitting and the GEMM.
 void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
-                 hipStream_t st);
+                 hipStream_t st, hipEvent_t ev_after_split = nullptr);
 // Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes of both operands.
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
 

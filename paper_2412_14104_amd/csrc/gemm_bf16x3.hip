@@ -244,7 +244,7 @@ size_t gemm_bf16x3_ws_doubles(const GemmArgs& g) {
 }
 
 void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
-                 hipStream_t st) {
+                 hipStream_t st, hipEvent_t ev_after_split) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   (void)planes_ws_doubles;
   const int64_t Kp = kpad(g.K);
@@ -275,6 +275,7 @@ void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
     hipLaunchKernelGGL(split3_kernel, grid, dim3(256), 0, st, g.B, g.N, g.K, g.ldb, g.sB,
                        g.tb ? 0 : 1, Kp, w + 3 * na, w + 3 * na + nb, w + 3 * na + 2 * nb);
   }
+  if (ev_after_split) (void)hipEventRecord(ev_after_split, st);
   dim3 grid((unsigned)(ba.tiles_m * ba.tiles_n), 1u, (unsigned)g.batch);
   hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(NT), 0, st, ba);
 }

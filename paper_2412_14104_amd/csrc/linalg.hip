@@ -66,7 +66,13 @@ __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, i
   __shared__ double2 pw[2][CW][RG / 2];   // per-column partial dot products of the RG groups
   __shared__ double rj[2][CW];            // row j of the block
   __shared__ double sclv[CW], betav[CW];
-  const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
+  // a wave holds 64 / RG whole columns (all RG row groups); once they are finished the wave
+  // only takes part in the barriers
+  constexpr int CPW = 64 / RG;
+  static_assert(64 % RG == 0 && (CW * RG) % 64 == 0, "waves hold whole columns");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int c_lo = __builtin_amdgcn_readfirstlane(tid >> 6) * CPW;  // first column of the wave
+  const int g = lane % RG, c = c_lo + lane / RG;
   const int64_t blk = blockIdx.x, r0 = blk * (int64_t)b;
   const int nb = (int)((rows - r0) < b ? (rows - r0) : b);
   double* pws = reinterpret_cast<double*>(pw);
@@ -115,6 +121,7 @@ __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, i
         }
       }
       __syncthreads();
+      if (c_lo + CPW <= j || c_lo >= n) continue;  // wave-uniform: all its columns finished
 
       auto colsum = [&](int cc) {
         double sum = 0.0;
@@ -135,7 +142,7 @@ __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, i
         t = (beta - alpha) / beta;
         scl = 1.0 / (alpha - beta);
       }
-      if (tid == 0) {
+      if (c == j && g == 0) {
         tau[blk * n + j] = t;
         sclv[j] = scl;
         betav[j] = beta;

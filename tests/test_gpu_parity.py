@@ -66,12 +66,15 @@ def test_free_energy_and_spectra_match_oracle(pkg, name):
 
 
 def test_c3_fp64_free_energy_matches_oracle(pkg):
+    """chi = 32, r = 3, 40 steps: the benchmark workload, against the oracle's stored run."""
     g = golden("C3")
     run = g["runs"][0]
     print("case C3 fp64", flush=True)
     eng = pkg.Engine(g["chi"], g["r"], g["q"], g["n_steps"], seed=g["seed"])
     f, lnzv = eng.run(run["beta"])
+    print("C3 fp64 |df|/|f| =", abs(f - run["f"]) / abs(run["f"]), flush=True)
     assert abs(f - run["f"]) <= REL_F * abs(run["f"]), (f, run["f"])
+    assert abs(lnzv - run["lnZV"]) <= REL_F * abs(run["lnZV"])
 
 
 def test_one_step_from_the_oracle_state(pkg):
@@ -140,7 +143,7 @@ def test_standalone_rsvd(pkg):
 REL_F_BF16 = 1e-6     # free-energy parity of the split-bf16 contraction path
 
 
-@pytest.mark.parametrize("name", ["C1", "C2"])
+@pytest.mark.parametrize("name", ["C1", "C2", "C3"])
 def test_split_bf16_free_energy_matches_oracle(pkg, name):
     g = golden(name)
     run = g["runs"][0]
