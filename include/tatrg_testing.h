@@ -22,7 +22,9 @@ extern "C" {
 /* C[b] = alpha op(A[b]) op(B[b]) + beta C[b]; op(A) M x K (A stored K x M when ta),
  * op(B) K x N (B stored N x K when tb); batch strides sA, sB, sC in elements.
  * parts > 1 splits K and sums the parts in order through `partial`
- * (parts * batch * M * N doubles). */
+ * (parts * batch * M * N doubles).  parts < 0 selects the skinny-product kernel for
+ * ta = 1, tb = 0, batch 1, M, N <= 96 (one wave per chunk of rows), with `partial` holding
+ * -parts * 1024 doubles; returns -1 when the shape does not qualify. */
 int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int64_t N,
                     int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
                     double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,

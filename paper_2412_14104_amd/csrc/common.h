@@ -33,6 +33,12 @@ void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
 // Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes of both operands.
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
 
+// C = alpha X^T Y + beta C for the skinny shapes X (K x M), Y (K x N) with M, N <= 96
+// (GemmArgs with ta && !tb, batch 1): one wave per chunk of rows writes an M x N partial
+// sum to `partial`, summed in a fixed order afterwards.  Returns false (nothing launched)
+// when the shape does not qualify or `partial` is too small.
+bool gram_tn(const GemmArgs& g, double* partial, size_t partial_doubles, hipStream_t st);
+
 // Long-K GEMM with small M x N: the K range is split into `parts` chunks written to
 // `partial` (parts * batch * M * N doubles) and summed in a fixed order (deterministic).
 void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t st);

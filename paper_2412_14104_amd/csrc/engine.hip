@@ -349,6 +349,7 @@ void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
 // Deterministic split-K for products with a small output and a long K: enough parts for
 // about four workgroups per compute unit, at least 128 values of K per part.
 void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
+  if (g.K >= 4096 && gram_tn(g, h->partial, h->partial_doubles, h->st)) return;
   const int64_t mn = g.M * g.N * g.batch;
   const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
   int64_t parts = (1024 + tiles - 1) / tiles;

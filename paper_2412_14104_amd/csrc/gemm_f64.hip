@@ -14,6 +14,8 @@
 // and parts are summed afterwards in a fixed order.
 #include "common.h"
 
+#include <algorithm>
+
 namespace tatrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -185,6 +187,86 @@ __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64
   }
 }
 
+// C = alpha * sum_p partial[p] + beta * C for many parts p of a small M x N output (one
+// batch): 64 outputs per work-group, 16 groups of threads each summing every 16th part in
+// increasing order, then the 16 group sums added in a fixed order (deterministic).
+__global__ __launch_bounds__(1024) void parts_reduce_kernel(const double* partial, double* C,
+                                                            int64_t M, int64_t N, int64_t ldc,
+                                                            int64_t parts, double alpha,
+                                                            double beta, const int* cond,
+                                                            int cond_when) {
+  if (cond && ((*cond != 0) != (cond_when != 0))) return;
+  __shared__ double acc[16][64];
+  const int tid = threadIdx.x, ol = tid & 63, pg = tid >> 6;
+  const int64_t mn = M * N, o = (int64_t)blockIdx.x * 64 + ol;
+  double sum = 0.0;
+  if (o < mn)
+    for (int64_t p = pg; p < parts; p += 16) sum += partial[p * mn + o];
+  acc[pg][ol] = sum;
+  __syncthreads();
+  if (pg == 0 && o < mn) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += acc[q][ol];
+    const int64_t i = o / N, j = o - (o / N) * N;
+    double* c = C + i * ldc + j;
+    double val = alpha * t;
+    if (beta != 0.0) val += beta * *c;
+    *c = val;
+  }
+}
+
+// Skinny products C = X^T Y with X (m x M), Y (m x N) row-major, M, N <= 16 NB, m long.
+// Every wave sums its own chunk of rows into partial[wave] (M x N); no LDS: a lane loads
+// its MFMA fragments straight from the rows (four rows per step, lane l reading row l/16,
+// column 16 b + l%16), so each step reads four contiguous rows.
+template <int NB>
+__global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t ldx,
+                                                      const double* Y, int64_t ldy, int64_t m,
+                                                      int M, int N, int64_t rows_per_wave,
+                                                      int64_t nwaves, double* partial,
+                                                      const int* cond, int cond_when) {
+  if (cond && ((*cond != 0) != (cond_when != 0))) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= nwaves) return;
+  const int64_t r0 = wid * rows_per_wave;
+  const int64_t r1 = (r0 + rows_per_wave < m) ? r0 + rows_per_wave : m;
+  const int kr = lane >> 4, cl = lane & 15;
+  d4 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int64_t r = r0; r < r1; r += 4) {
+    const int64_t row = r + kr;
+    const bool ok = row < r1;
+    double xa[NB], yb[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int col = b * 16 + cl;
+      xa[b] = (ok && col < M) ? X[row * ldx + col] : 0.0;
+      yb[b] = (ok && col < N) ? Y[row * ldy + col] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
+  }
+  double* out = partial + wid * (int64_t)M * N;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + (lane >> 4) + 4 * v, col = j * 16 + cl;
+        if (row < M && col < N) out[row * N + col] = acc[i][j][v];
+      }
+}
+
 template <bool TA, bool TB>
 void launch_b(const KArgs& ka, dim3 grid, hipStream_t st) {
   const bool plain = ka.kparts > 1 || (ka.g.alpha == 1.0 && ka.g.beta == 0.0);
@@ -211,6 +293,35 @@ void launch(const KArgs& ka, hipStream_t st) {
 void gemm_f64(const GemmArgs& g, hipStream_t st) {
   KArgs ka{g, 1, g.K, nullptr};
   launch(ka, st);
+}
+
+bool gram_tn(const GemmArgs& g, double* partial, size_t partial_doubles, hipStream_t st) {
+  if (!(g.ta && !g.tb) || g.batch != 1 || g.M > 96 || g.N > 96 || g.M < 1 || g.N < 1)
+    return false;
+  const int64_t mn = g.M * g.N;
+  int64_t nw = std::min<int64_t>(2048, (g.K + 63) / 64);   // >= 64 rows per wave
+  nw = std::min<int64_t>(nw, (int64_t)(partial_doubles / (size_t)mn));
+  if (nw < 1) return false;
+  int64_t rpw = (g.K + nw - 1) / nw;
+  rpw = ((rpw + 3) / 4) * 4;
+  nw = (g.K + rpw - 1) / rpw;
+  const int nbk = (int)((std::max(g.M, g.N) + 15) / 16);
+  const dim3 grid((unsigned)((nw + 3) / 4));
+  const int cw = g.cond_when ? 1 : 0;
+  switch (nbk) {
+#define GRAM_CASE(NB)                                                                         \
+  case NB:                                                                                    \
+    hipLaunchKernelGGL(gram_tn_kernel<NB>, grid, dim3(256), 0, st, g.A, g.lda, g.B, g.ldb,   \
+                       g.K, (int)g.M, (int)g.N, rpw, nw, partial, g.cond, cw);                \
+    break;
+    GRAM_CASE(1) GRAM_CASE(2) GRAM_CASE(3) GRAM_CASE(4) GRAM_CASE(5) GRAM_CASE(6)
+#undef GRAM_CASE
+    default:
+      return false;
+  }
+  hipLaunchKernelGGL(parts_reduce_kernel, dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0, st,
+                     partial, g.C, g.M, g.N, g.ldc, nw, g.alpha, g.beta, g.cond, cw);
+  return true;
 }
 
 void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t st) {

@@ -115,6 +115,26 @@ def test_gemm_split_k_is_deterministic_and_correct(lib):
     assert np.all(np.abs(outs[0] - a @ b) <= gemm_bound(a, b, k))
 
 
+@pytest.mark.parametrize("m,n,k", [(32, 32, 1048576), (96, 96, 5000), (40, 17, 100003),
+                                   (1, 1, 4096)])
+def test_skinny_gram_kernel(lib, m, n, k):
+    """C = alpha X^T Y + beta C with X (k x m), Y (k x n): the kernel behind the long Grams."""
+    rng = np.random.default_rng(m + n + k)
+    x = rng.standard_normal((k, m))
+    y = x[:, :n].copy() if n <= m else rng.standard_normal((k, n))
+    y[::7] *= -1.0
+    c0 = rng.standard_normal((m, n))
+    dx, dy, dc = dev(x), dev(y), dev(c0)
+    part = torch.empty(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    rc = lib.tatrg_test_gemm(vp(dx), vp(dy), vp(dc), m, n, k, m, n, n, 1, 0, 0.5, 2.0, 1, 0, 0,
+                             0, -(part.numel() // 1024), vp(part), stream())
+    assert rc == 0
+    ref = 0.5 * x.T @ y + 2.0 * c0
+    bound = 0.5 * gemm_bound(x.T, y, k) + 2.0 * np.abs(c0) * 1e-16
+    got = host(dc)
+    assert np.all(np.abs(got - ref) <= bound), np.abs(got - ref).max()
+
+
 TSQR_CASES = [(10, 1), (100, 7), (1000, 32), (5000, 96), (300000, 32), (120000, 96), (96, 96)]
 
 
