@@ -24,7 +24,9 @@ extern "C" {
  * parts > 1 splits K and sums the parts in order through `partial`
  * (parts * batch * M * N doubles).  parts < 0 selects the skinny-product kernel for
  * ta = 1, tb = 0, batch 1, M, N <= 96 (one wave per chunk of rows), with `partial` holding
- * -parts * 1024 doubles; returns -1 when the shape does not qualify. */
+ * -parts * 1024 doubles; returns -1 when the shape does not qualify.  With A == B (same
+ * pointer, stride and leading dimension), M == N and ta != tb the product is symmetric and
+ * split-K computes only the tiles on and above the diagonal, mirroring the rest. */
 int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int64_t N,
                     int64_t K, int64_t lda, int64_t ldb, int64_t ldc, int ta, int tb,
                     double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,

@@ -22,6 +22,9 @@ struct GemmArgs {
   // (*cond != 0) == cond_when (lets a fallback path be launched without a host sync).
   const int* cond = nullptr;
   bool cond_when = false;
+  // Symmetric output (op(A) op(B) = X X^T with M = N): split-K computes the tiles on and
+  // above the diagonal only and its reduction mirrors them.
+  bool sym = false;
 };
 void gemm_f64(const GemmArgs& g, hipStream_t st);
 

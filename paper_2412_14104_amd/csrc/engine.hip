@@ -346,21 +346,34 @@ void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
   }
 }
 
-// Deterministic split-K for products with a small output and a long K: enough parts for
-// about four workgroups per compute unit, at least 128 values of K per part.
+// Deterministic split-K for products with a small output and a long K.  The part count fills
+// whole rounds of the chip (256 CUs x 2 resident GEMM work-groups) with the tiles that run
+// -- for a symmetric product only those on and above the diagonal -- keeping at least 128
+// values of K per part and within the partial-sum buffer.
 void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
   if (g.K >= 4096 && gram_tn(g, h->partial, h->partial_doubles, h->st)) return;
+  constexpr int64_t SLOTS = 512;
   const int64_t mn = g.M * g.N * g.batch;
-  const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-  int64_t parts = (1024 + tiles - 1) / tiles;
-  parts = std::min<int64_t>(parts, g.K / 128);
-  parts = std::min<int64_t>(parts, (int64_t)(h->partial_doubles / (size_t)mn));
-  parts = std::min<int64_t>(parts, 2048);
-  if (tiles >= 256 || parts < 2) {
+  const int64_t tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+  const int64_t tiles = tm * tn * g.batch;
+  if (tiles >= 256) {
     gemm_f64(g, h->st);
     return;
   }
-  gemm_f64_splitk(g, (int)parts, h->partial, h->st);
+  GemmArgs gs = g;
+  gs.sym = g.A == g.B && g.lda == g.ldb && g.ta != g.tb && g.M == g.N && g.sA == g.sB;
+  const int64_t active = gs.sym ? tm * (tm + 1) / 2 * g.batch : tiles;
+  const int64_t cap = std::min<int64_t>(
+      std::min<int64_t>(g.K / 128, (int64_t)(h->partial_doubles / (size_t)mn)), 2048);
+  int64_t rounds = (active * ((1024 + tiles - 1) / tiles) + SLOTS - 1) / SLOTS;
+  int64_t parts = rounds * SLOTS / active;
+  while (parts > cap && rounds > 1) parts = --rounds * SLOTS / active;
+  parts = std::min(parts, cap);
+  if (parts < 2) {
+    gemm_f64(g, h->st);
+    return;
+  }
+  gemm_f64_splitk(gs, (int)parts, h->partial, h->st);
 }
 
 // Orthonormal basis of a tall panel Y (m x n, ld), in place: Y <- Q with Y_in = Q R.

@@ -39,6 +39,18 @@ template <bool TA, bool TB, bool PLAIN>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const GemmArgs& g = ka.g;
   if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
+  // tile: blockIdx.(x, y) = (N tile, M tile); for a symmetric split-K product blockIdx.x
+  // enumerates the tiles on and above the diagonal column by column, t = tn (tn + 1) / 2 + tm,
+  // so consecutive work-groups (which the dispatcher spreads over the XCDs) share the load
+  int tile_m = blockIdx.y, tile_n = blockIdx.x;
+  if (g.sym && ka.kparts > 1) {
+    const int t = blockIdx.x;
+    int tn = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((tn + 1) * (tn + 2) / 2 <= t) ++tn;
+    while (tn * (tn + 1) / 2 > t) --tn;
+    tile_n = tn;
+    tile_m = t - tn * (tn + 1) / 2;
+  }
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
@@ -54,8 +66,8 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
 
   const double* A = g.A + b * g.sA + (TA ? kb * g.lda : kb);
   const double* B = g.B + b * g.sB + (TB ? kb : kb * g.ldb);
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t m0 = (int64_t)tile_m * BM;
+  const int64_t n0 = (int64_t)tile_n * BN;
   const int64_t M = g.M, N = g.N;
 
   // element e of a stage: A tile row/k and B tile column/k
@@ -166,10 +178,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
       }
 }
 
-// C[b] = alpha * sum_p partial[b][p] + beta * C[b], parts summed in increasing p.
+// C[b] = alpha * sum_p partial[b][p] + beta * C[b], parts summed in increasing p.  With sym,
+// the partial sums exist for the 128 x 128 tiles on and above the diagonal only, and element
+// (i, j) of a tile below it is read from (j, i).
 __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64_t N,
                               int64_t ldc, int64_t sC, int kparts, int64_t batch, double alpha,
-                              double beta, const int* cond, int cond_when) {
+                              double beta, const int* cond, int cond_when, int sym) {
   if (cond && ((*cond != 0) != (cond_when != 0))) return;
   const int64_t total = batch * M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -177,7 +191,8 @@ __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64
     const int64_t b = idx / (M * N);
     const int64_t r = idx - b * M * N;
     const int64_t i = r / N, j = r - (r / N) * N;
-    const double* pp = partial + b * kparts * M * N + r;
+    const int64_t src = (sym && i / BM > j / BN) ? j * N + i : r;
+    const double* pp = partial + b * kparts * M * N + src;
     double s = 0.0;
     for (int p = 0; p < kparts; ++p) s += pp[(int64_t)p * M * N];
     double* c = C + b * sC + i * ldc + j;
@@ -277,8 +292,10 @@ void launch_b(const KArgs& ka, dim3 grid, hipStream_t st) {
 void launch(const KArgs& ka, hipStream_t st) {
   const GemmArgs& g = ka.g;
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
-            (unsigned)(g.batch * ka.kparts));
+  const int64_t tn = (g.N + BN - 1) / BN, tm = (g.M + BM - 1) / BM;
+  dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(g.batch * ka.kparts));
+  if (g.sym && ka.kparts > 1) grid = dim3((unsigned)(tn * (tn + 1) / 2), 1u,
+                                          (unsigned)(g.batch * ka.kparts));
   if (g.ta) {
     if (g.tb) launch_b<true, true>(ka, grid, st);
     else launch_b<true, false>(ka, grid, st);
@@ -338,9 +355,10 @@ void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t 
   const int threads = 256;
   int64_t blocks = (total + threads - 1) / threads;
   if (blocks > 65535) blocks = 65535;
+  const int sym = (g.sym && g.M == g.N) ? 1 : 0;
   hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, partial, g.C,
                      g.M, g.N, g.ldc, g.sC, used, g.batch, g.alpha, g.beta, g.cond,
-                     g.cond_when ? 1 : 0);
+                     g.cond_when ? 1 : 0, sym);
 }
 
 }  // namespace tatrg

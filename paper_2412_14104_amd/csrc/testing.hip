@@ -19,6 +19,7 @@ int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int6
   g.B = B; g.ldb = ldb; g.sB = sB; g.tb = tb != 0;
   g.C = C; g.ldc = ldc; g.sC = sC;
   g.alpha = alpha; g.beta = beta; g.batch = batch;
+  g.sym = A == B && lda == ldb && g.ta != g.tb && M == N && sA == sB;
   if (parts < 0) {
     if (!partial) return -1;
     if (!gram_tn(g, partial, (size_t)(-(int64_t)parts) * 1024, (hipStream_t)stream)) return -1;

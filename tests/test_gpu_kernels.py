@@ -115,6 +115,25 @@ def test_gemm_split_k_is_deterministic_and_correct(lib):
     assert np.all(np.abs(outs[0] - a @ b) <= gemm_bound(a, b, k))
 
 
+@pytest.mark.parametrize("m,k,ta", [(300, 20000, False), (1024, 32768, False), (257, 9000, True)])
+def test_symmetric_split_k_gram(lib, m, k, ta):
+    """X X^T (or X^T X) through split-K with one operand: upper tiles computed, lower mirrored."""
+    rng = np.random.default_rng(m + k)
+    x = rng.standard_normal((k, m) if ta else (m, k))
+    dx = dev(x)
+    dc = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    parts = 8
+    part = torch.empty(parts * m * m, dtype=torch.float64, device="cuda")
+    ld = x.shape[1]
+    assert lib.tatrg_test_gemm(vp(dx), vp(dx), vp(dc), m, m, k, ld, ld, m, int(ta), int(not ta),
+                               1.0, 0.0, 1, 0, 0, 0, parts, vp(part), stream()) == 0
+    got = host(dc)
+    ref = x.T @ x if ta else x @ x.T
+    xx = x.T if ta else x
+    assert np.array_equal(got, got.T)
+    assert np.all(np.abs(got - ref) <= gemm_bound(xx, xx.T, k))
+
+
 @pytest.mark.parametrize("m,n,k", [(32, 32, 1048576), (96, 96, 5000), (40, 17, 100003),
                                    (1, 1, 4096)])
 def test_skinny_gram_kernel(lib, m, n, k):
