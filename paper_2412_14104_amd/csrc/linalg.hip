@@ -55,7 +55,12 @@ TsqrShape tsqr_shape(int n) {
 // is row slot kk = j / RG of group j % RG; the column loop runs as an unrolled loop over kk
 // around a loop over the group, so that slot is a compile-time register index.  Scaling of
 // the stored reflector and the diagonal beta are applied when the block is written out.
-template <int CW, int RG, int RPG>
+//
+// TRI: the block is two stacked upper-triangular n x n factors (a tree level with
+// n = RG * RPG / 2).  Then column j of the Householder vector is nonzero only in rows
+// n .. n + j, i.e. in register slots RPG/2 .. RPG/2 + j/RG, and the dot, update and rebuild
+// loops run over those slots only (the skipped products are with exact zeros).
+template <int CW, int RG, int RPG, bool TRI>
 __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, int64_t rows,
                                                           int64_t lds, int b, int n, double* v,
                                                           int64_t ldv, double* tau,
@@ -108,7 +113,8 @@ __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, i
       if (c >= j && c < n) {
         double p = 0.0;
 #pragma unroll
-        for (int k = 0; k < RPG; ++k) p += x[k] * a[k];
+        for (int k = 0; k < RPG; ++k)
+          if (!TRI || (k >= RPG / 2 && k <= RPG / 2 + kk)) p += x[k] * a[k];
         pws[((bf * CW) + c) * RG + g] = p;
         if (g == jg) rj[bf][c] = a[kk];
       }
@@ -150,13 +156,15 @@ __global__ __launch_bounds__(CW * RG) void hh_factor_kernel(const double* src, i
       if (c > j && c < n) {
         const double tw = t * (rj[bf][c] + scl * colsum(c)), f = tw * scl;
 #pragma unroll
-        for (int k = 0; k < RPG; ++k) a[k] -= f * x[k];
+        for (int k = 0; k < RPG; ++k)
+          if (!TRI || (k >= RPG / 2 && k <= RPG / 2 + kk)) a[k] -= f * x[k];
         if (g == jg) a[kk] -= tw;
       }
       if (j + 1 < n) {
         const double tw = t * (rj[bf][j + 1] + scl * colsum(j + 1)), f = tw * scl;
 #pragma unroll
         for (int k = 0; k < RPG; k += 2) {
+          if (TRI && (k + 1 < RPG / 2 || k > RPG / 2 + kk + 1)) continue;  // zero rows of x
           const double2 e = xp[bf ^ 1][g][k / 2];
           x[k] = e.x - f * x[k];
           x[k + 1] = e.y - f * x[k + 1];
@@ -609,8 +617,14 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double*
 template <int CW, int RG, int RPG>
 void tsqr_level_launch(bool apply, const TsqrLevel& L, int n, const double* cin,
                        const int* run_if, hipStream_t st) {
-  if (!apply)
-    hipLaunchKernelGGL((hh_factor_kernel<CW, RG, RPG>), dim3((unsigned)L.nblocks),
+  // two stacked triangular factors that fill the slots exactly: structured factorisation
+  const bool tri = !L.leaf && L.b == 2 * n && n == RG * RPG / 2;
+  if (!apply && tri)
+    hipLaunchKernelGGL((hh_factor_kernel<CW, RG, RPG, true>), dim3((unsigned)L.nblocks),
+                       dim3(CW * RG), 0, st, L.src, L.rows, L.ld, L.b, n, L.v, L.ld, L.tau,
+                       L.rstack, run_if);
+  else if (!apply)
+    hipLaunchKernelGGL((hh_factor_kernel<CW, RG, RPG, false>), dim3((unsigned)L.nblocks),
                        dim3(CW * RG), 0, st, L.src, L.rows, L.ld, L.b, n, L.v, L.ld, L.tau,
                        L.rstack, run_if);
   else
