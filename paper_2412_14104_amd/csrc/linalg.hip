@@ -593,12 +593,15 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double*
                                                           : (d > 0.25 && d < 4.0));
     if (!ok && tid == 0) bad = 1;
     const double rd = 1.0 / (ok ? d : 1.0);
-    const int m = n - k - 1;
-    for (int idx = tid; idx < m * n; idx += 1024) {
-      const int i = k + 1 + idx / n, q = idx - (idx / n) * n;
-      const double mi = A[k][i] * rd;
-      if (q >= i) A[i][q] -= mi * A[k][q];
-      else if (q <= k) E[i][q] -= mi * E[k][q];
+    // thread (q, gr) = (tid % 128, tid / 128): column q of rows k+1+gr, k+9+gr, ...
+    const int q = tid & 127, gr = tid >> 7;
+    if (q < n) {
+      const double akq = A[k][q], ekq = E[k][q];
+      for (int i = k + 1 + gr; i < n; i += 8) {
+        const double mi = A[k][i] * rd;
+        if (q >= i) A[i][q] -= mi * akq;
+        else if (q <= k) E[i][q] -= mi * ekq;
+      }
     }
     __syncthreads();
   }
