@@ -562,7 +562,7 @@ void bond_swap(tatrg_handle* h, double* rec) {
   SwapOp op;
   op.h = h;
   op.right_split = d.n3;  // sketch rows (beta, b') stored in (b', beta) order
-  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, false);
+  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true);
   // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c] (Qb rows in (b', beta))
   gemm(h, G(d.n4, c, w, h->P2, w, false, h->Uh, w, false, h->Xs, c));
   perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
