@@ -619,7 +619,7 @@ void isometries(tatrg_handle* h) {
     op.M = h->rho + z * n2 * n2;
     op.n = n2;
     double* U = h->UZ + z * n2 * d.L;
-    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, false);
+    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, true);
   }
 }
 
