@@ -234,8 +234,10 @@ __global__ __launch_bounds__(1024) void parts_reduce_kernel(const double* partia
 // Skinny products C = X^T Y with X (m x M), Y (m x N) row-major, M, N <= 16 NB, m long.
 // Every wave sums its own chunk of rows into partial[wave] (M x N); no LDS: a lane loads
 // its MFMA fragments straight from the rows (four rows per step, lane l reading row l/16,
-// column 16 b + l%16), so each step reads four contiguous rows.
-template <int NB>
+// column 16 b + l%16), so each step reads four contiguous rows.  SYM (X = Y, M = N): only
+// the 16 x 16 blocks on and above the diagonal are accumulated and each is also written
+// transposed below it.
+template <int NB, bool SYM>
 __global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t ldx,
                                                       const double* Y, int64_t ldy, int64_t m,
                                                       int M, int N, int64_t rows_per_wave,
@@ -262,24 +264,30 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t l
     for (int b = 0; b < NB; ++b) {
       const int col = b * 16 + cl;
       xa[b] = (ok && col < M) ? X[row * ldx + col] : 0.0;
-      yb[b] = (ok && col < N) ? Y[row * ldy + col] : 0.0;
+      yb[b] = SYM ? xa[b] : ((ok && col < N) ? Y[row * ldy + col] : 0.0);
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
+        if (!SYM || i <= j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
   }
   double* out = partial + wid * (int64_t)M * N;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NB; ++j) {
+      if (SYM && i > j) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = i * 16 + (lane >> 4) + 4 * v, col = j * 16 + cl;
-        if (row < M && col < N) out[row * N + col] = acc[i][j][v];
+        if (row < M && col < N) {
+          out[row * N + col] = acc[i][j][v];
+          if (SYM && i < j) out[col * N + row] = acc[i][j][v];
+        }
       }
+    }
 }
 
 template <bool TA, bool TB>
@@ -325,11 +333,16 @@ bool gram_tn(const GemmArgs& g, double* partial, size_t partial_doubles, hipStre
   const int nbk = (int)((std::max(g.M, g.N) + 15) / 16);
   const dim3 grid((unsigned)((nw + 3) / 4));
   const int cw = g.cond_when ? 1 : 0;
+  const bool sym = g.A == g.B && g.lda == g.ldb && g.M == g.N;
   switch (nbk) {
 #define GRAM_CASE(NB)                                                                         \
   case NB:                                                                                    \
-    hipLaunchKernelGGL(gram_tn_kernel<NB>, grid, dim3(256), 0, st, g.A, g.lda, g.B, g.ldb,   \
-                       g.K, (int)g.M, (int)g.N, rpw, nw, partial, g.cond, cw);                \
+    if (sym)                                                                                  \
+      hipLaunchKernelGGL((gram_tn_kernel<NB, true>), grid, dim3(256), 0, st, g.A, g.lda, g.B, \
+                         g.ldb, g.K, (int)g.M, (int)g.N, rpw, nw, partial, g.cond, cw);       \
+    else                                                                                      \
+      hipLaunchKernelGGL((gram_tn_kernel<NB, false>), grid, dim3(256), 0, st, g.A, g.lda,     \
+                         g.B, g.ldb, g.K, (int)g.M, (int)g.N, rpw, nw, partial, g.cond, cw);  \
     break;
     GRAM_CASE(1) GRAM_CASE(2) GRAM_CASE(3) GRAM_CASE(4) GRAM_CASE(5) GRAM_CASE(6)
 #undef GRAM_CASE

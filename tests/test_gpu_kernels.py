@@ -134,16 +134,23 @@ def test_symmetric_split_k_gram(lib, m, k, ta):
     assert np.all(np.abs(got - ref) <= gemm_bound(xx, xx.T, k))
 
 
-@pytest.mark.parametrize("m,n,k", [(32, 32, 1048576), (96, 96, 5000), (40, 17, 100003),
-                                   (1, 1, 4096)])
-def test_skinny_gram_kernel(lib, m, n, k):
-    """C = alpha X^T Y + beta C with X (k x m), Y (k x n): the kernel behind the long Grams."""
+@pytest.mark.parametrize("m,n,k,same", [(32, 32, 1048576, False), (96, 96, 5000, False),
+                                        (40, 17, 100003, False), (1, 1, 4096, False),
+                                        (96, 96, 300001, True), (32, 32, 1048576, True),
+                                        (70, 70, 9000, True)])
+def test_skinny_gram_kernel(lib, m, n, k, same):
+    """C = alpha X^T Y + beta C with X (k x m), Y (k x n): the kernel behind the long Grams;
+    same=True passes one buffer as X and Y (the symmetric variant, upper blocks mirrored)."""
     rng = np.random.default_rng(m + n + k)
     x = rng.standard_normal((k, m))
-    y = x[:, :n].copy() if n <= m else rng.standard_normal((k, n))
-    y[::7] *= -1.0
+    if same:
+        y = x
+    else:
+        y = x[:, :n].copy() if n <= m else rng.standard_normal((k, n))
+        y[::7] *= -1.0
     c0 = rng.standard_normal((m, n))
-    dx, dy, dc = dev(x), dev(y), dev(c0)
+    dx, dc = dev(x), dev(c0)
+    dy = dx if same else dev(y)
     part = torch.empty(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
     rc = lib.tatrg_test_gemm(vp(dx), vp(dy), vp(dc), m, n, k, m, n, n, 1, 0, 0.5, 2.0, 1, 0, 0,
                              0, -(part.numel() // 1024), vp(part), stream())
