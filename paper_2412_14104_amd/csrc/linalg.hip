@@ -562,58 +562,84 @@ __global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int*
 // Symmetric elimination on the upper triangle: step k subtracts m_i = A[k][i] / d_k times row
 // k from every row i > k (d_k = A[k][k], the k-th pivot of G = L D L^T).  The same row
 // operations applied to the identity build E = L^{-1}, so R = D^{1/2} L^T and
-// R^{-1} = E^T D^{-1/2} come out of one pass with one barrier per pivot.
+// R^{-1} = E^T D^{-1/2} come out of one pass.
+//
+// Thread (q, g) = (tid % 128, tid / 128) keeps column q of A and of E for rows g + 8 s
+// (s < 12) in registers.  At step k the threads holding row k publish it (A[k][.] and
+// E[k][.]) to a double-buffered LDS vector; after one barrier every thread updates its rows
+// below k.  The step loop runs as an unrolled loop over the register slot of row k around a
+// loop over its group, so every register index is static.
 __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double* R, double* Ri,
                                                          int n, int pass, int* fail,
                                                          double shift_coef) {
-  __shared__ double A[96][97];
-  __shared__ double E[96][97];
+  constexpr int RGP = 8, SL = 12;  // row groups and slots: 96 rows
+  __shared__ double ra[2][128], re[2][128], dv[96];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, q = tid & 127, g = tid >> 7;
   if (*fail) return;  // uniform: read before any write of this launch
-  for (int idx = tid; idx < n * n; idx += 1024) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    A[i][j] = G[idx];
-    E[i][j] = (i == j) ? 1.0 : 0.0;
+  double a[SL], e[SL];
+  double tr = 0.0, dmax = 0.0;
+  for (int k = 0; k < n; ++k) {  // diagonal of G: trace and largest entry (every thread)
+    const double dk = G[k * n + k];
+    tr += dk;
+    dmax = fmax(dmax, dk);
+  }
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int i = g + RGP * s;
+    double x = (i < n && q < n) ? G[i * n + q] : 0.0;
+    if (pass == 0 && i == q && i < n) x += shift_coef * tr;  // ||Y||_2^2 <= tr(G)
+    a[s] = x;
+    e[s] = (i == q && i < n) ? 1.0 : 0.0;
   }
   if (tid == 0) bad = 0;
-  __syncthreads();
-  double dmax = 0.0, tr = 0.0;
-  for (int k = 0; k < n; ++k) {
-    dmax = fmax(dmax, A[k][k]);
-    tr += A[k][k];
-  }
-  __syncthreads();
-  if (pass == 0 && tid < n) A[tid][tid] += shift_coef * tr;  // ||Y||_2^2 <= tr(G)
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double d = A[k][k];
-    const bool ok = isfinite(d) && (pass == 0 ? d > 0.0
-                                              : pass == 1 ? d > 1e-14 * dmax
-                                                          : (d > 0.25 && d < 4.0));
-    if (!ok && tid == 0) bad = 1;
-    const double rd = 1.0 / (ok ? d : 1.0);
-    // thread (q, gr) = (tid % 128, tid / 128): column q of rows k+1+gr, k+9+gr, ...
-    const int q = tid & 127, gr = tid >> 7;
-    if (q < n) {
-      const double akq = A[k][q], ekq = E[k][q];
-      for (int i = k + 1 + gr; i < n; i += 8) {
-        const double mi = A[k][i] * rd;
-        if (q >= i) A[i][q] -= mi * akq;
-        else if (q <= k) E[i][q] -= mi * ekq;
+#pragma unroll
+  for (int kk = 0; kk < SL; ++kk) {
+#pragma unroll 1
+    for (int kg = 0; kg < RGP; ++kg) {
+      const int k = kk * RGP + kg, bf = k & 1;
+      if (k >= n) break;
+      if (g == kg && q < n) {  // this thread holds row k of its column
+        ra[bf][q] = a[kk];
+        re[bf][q] = e[kk];
+      }
+      __syncthreads();
+      const double d = ra[bf][k];
+      const bool ok = isfinite(d) && (pass == 0 ? d > 0.0
+                                                : pass == 1 ? d > 1e-14 * dmax
+                                                            : (d > 0.25 && d < 4.0));
+      if (tid == 0) {
+        if (!ok) bad = 1;
+        dv[k] = d;
+      }
+      const double rd = 1.0 / (ok ? d : 1.0);
+      if (q < n) {
+        const double akq = ra[bf][q], ekq = re[bf][q];
+#pragma unroll
+        for (int s = kk; s < SL; ++s) {
+          const int i = g + RGP * s;
+          if (i <= k || i >= n) continue;
+          const double mi = ra[bf][i] * rd;
+          if (q >= i) a[s] -= mi * akq;
+          else if (q <= k) e[s] -= mi * ekq;
+        }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (bad) {
     if (tid == 0) *fail = 1;
     return;
   }
-  for (int idx = tid; idx < n * n; idx += 1024) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    const double di = A[i][i], dj = A[j][j];
-    R[idx] = (j > i) ? A[i][j] / sqrt(di) : (j == i ? sqrt(di) : 0.0);
-    Ri[idx] = (j >= i) ? E[j][i] / sqrt(dj) : 0.0;
+  if (q < n) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = g + RGP * s;
+      if (i >= n) continue;
+      // R[i][q] from row i of A; R^{-1}[q][i] = E[i][q] / sqrt(d_i) (E lower triangular)
+      R[i * n + q] = (q > i) ? a[s] / sqrt(dv[i]) : (q == i ? sqrt(dv[i]) : 0.0);
+      Ri[q * n + i] = (q <= i) ? e[s] / sqrt(dv[i]) : 0.0;
+    }
   }
 }
 
