@@ -64,8 +64,8 @@ int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag
  * building block of the CholeskyQR orthonormalisation.  pass 0 factors
  * G + shift_coef * tr(G) * I and fails only on a non-positive or non-finite pivot; pass 1
  * fails when a pivot (of L D L^T) is <= 1e-14 of the largest diagonal entry; pass 2 when a
- * pivot leaves (0.25, 4).  A failure sets *fail = 1 (device int, left untouched otherwise;
- * nothing is computed when it is already set) and R, Rinv are then not written. */
+ * pivot leaves (0.25, 4).  A failure sets *fail = pass + 1 (device int, left untouched
+ * otherwise; nothing is computed when it is already set) and R, Rinv are then not written. */
 int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pass,
                         double shift_coef, int* fail, void* stream);
 

@@ -57,9 +57,10 @@ void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hi
 
 // Cholesky factor of an n x n Gram G = R^T R (n <= 96, one workgroup) with its inverse.
 // pass 0 factors G + shift_coef * tr(G) * I (the shifted first pass of CholeskyQR3) and fails
-// only on a non-finite or non-positive pivot; pass 1 raises *fail when a pivot is <= 1e-14 of
-// the largest diagonal entry; pass 2 (G close to the identity) raises it when a pivot leaves
-// (0.25, 4).  Does nothing when *fail is already set.
+// only on a non-finite or non-positive pivot; pass 1 fails when a pivot is <= 1e-14 of the
+// largest diagonal entry; pass 2 (G close to the identity) when a pivot leaves (0.25, 4).  A
+// failure sets *fail = pass + 1 and leaves R, Rinv unwritten.  Does nothing when *fail is
+// already set.
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
               hipStream_t st, double shift_coef = 0.0);
 

@@ -313,22 +313,6 @@ bool hip_ok(tatrg_handle* h, const char* where) {
 
 void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
 
-// dst[i][j] = src[i][j] for an m x n panel (leading dims lds, ldd).
-__global__ void copy_panel_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
-                                  int64_t m, int n) {
-  const int64_t total = m * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx / n, j = idx - (idx / n) * n;
-    dst[i * ldd + j] = src[i * lds + j];
-  }
-}
-void copy_panel(tatrg_handle* h, const double* src, int64_t lds, double* dst, int64_t ldd,
-                int64_t m, int n) {
-  hipLaunchKernelGGL(copy_panel_kernel, dim3(grid_for(m * n)), dim3(TPB), 0, h->st, src, lds,
-                     dst, ldd, m, n);
-}
-
 // The contraction GEMMs, bracketed by events when live timing is on (on the split path the
 // bracket starts after the plane splitting, so it times the GEMM kernel alone).
 void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
@@ -376,18 +360,36 @@ void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
   gemm_f64_splitk(gs, (int)parts, h->partial, h->st);
 }
 
-// Orthonormal basis of a tall panel Y (m x n, ld), in place: Y <- Q with Y_in = Q R.
+// dst <- src (m x n panels) when lo <= *flag <= hi.
+__global__ void copy_panel_when_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
+                                       int64_t m, int n, const int* flag, int lo, int hi) {
+  const int f = *flag;
+  if (f < lo || f > hi) return;
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx - (idx / n) * n;
+    dst[i * ldd + j] = src[i * lds + j];
+  }
+}
+
+// Orthonormal basis of a tall panel Y (m x n, ld, n <= 96), in place: Y <- Q with Y_in = Q R.
 // Shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020): a first
 // Cholesky pass on the Gram plus the shift 11 (mn + n(n+1)) u ||Y||^2 makes the panel
 // well conditioned, two plain passes make it orthonormal; Grams and products run on the
-// FP64 MFMA GEMM.  A panel that is rank deficient (a pivot of the second pass below 1e-14 of
-// the largest) is factorised by the Householder TSQR instead.  The choice is a device flag:
-// both paths are launched and each kernel of the unused one returns at once.  Both give the
-// same span up to rounding.
+// FP64 MFMA.  A pivot check that fails (the panel is numerically rank deficient) hands the
+// panel to the Householder TSQR instead.  The choice is a device flag: both paths are
+// launched and each kernel of the unused one returns at once.  Both give the same span up to
+// rounding.
+//   pass 0: P3 = Y R0^-1        pass 1: Y = P3 R1^-1        pass 2: Y = Y R2^-1 (in place:
+//   with n <= 128 each GEMM work-group reads its whole row block before writing it).
+// The flag records the failing pass (chol_inv sets pass + 1): after a failure in pass 0 Y
+// still holds the input and R = R_tsqr; after one in pass 1 or 2 the pass-0 panel P3 is
+// copied back and R = R_tsqr R0.
 void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_out,
           bool try_cholqr) {
   hipStream_t st = h->st;
-  if (!try_cholqr) {  // sketch panels that are usually numerically rank deficient
+  if (!try_cholqr) {
     tsqr(Y, m, n, ld, R_out, h->tsqr_ws, st, nullptr);
     return;
   }
@@ -401,46 +403,38 @@ void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_ou
   double* Rt = h->Gq + 5 * sq;
   const double shift = 11.0 * ((double)m * n + (double)n * (n + 1)) * 1.1102230246251565e-16;
   zero((double*)fail, 1, st);
-  // pass 0 (shifted): Y -> P3 = Y R0^-1
+  auto when_ok = [&](GemmArgs g) {
+    g.cond = fail;
+    g.cond_when = false;
+    return g;
+  };
+  // pass 0 (shifted)
   gemm_long_k(h, G(n, n, m, Y, ld, true, Y, ld, false, G1, n));
   chol_inv(G1, R0, Ri, n, 0, fail, st, shift);
-  gemm(h, G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n));
-  // pass 1: P3 -> Y = P3 R1^-1 (kept only when pass 2 succeeds; Y is overwritten here, so the
-  // fallback factorises the pass-0 panel P3 instead, which spans the same space)
-  gemm_long_k(h, G(n, n, m, h->P3, n, true, h->P3, n, false, G1, n));
+  gemm(h, when_ok(G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n)));
+  // pass 1
+  gemm_long_k(h, when_ok(G(n, n, m, h->P3, n, true, h->P3, n, false, G1, n)));
   chol_inv(G1, R1, Ri, n, 1, fail, st);
-  GemmArgs p1 = G(m, n, n, h->P3, n, false, Ri, n, false, Y, ld);
-  p1.cond = fail;
-  p1.cond_when = false;
-  gemm(h, p1);
-  // pass 2: Y -> P3 = Y R2^-1 -> copied back
-  GemmArgs g2 = G(n, n, m, Y, ld, true, Y, ld, false, G1, n);
-  gemm_long_k(h, g2);
+  gemm(h, when_ok(G(m, n, n, h->P3, n, false, Ri, n, false, Y, ld)));
+  // pass 2, in place
+  gemm_long_k(h, when_ok(G(n, n, m, Y, ld, true, Y, ld, false, G1, n)));
   chol_inv(G1, R2, Ri, n, 2, fail, st);
-  GemmArgs p2 = G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n);
-  p2.cond = fail;
-  p2.cond_when = false;
-  gemm(h, p2);
-  // Y <- P3: on success the orthonormal factor, on failure the pass-0 panel for the TSQR
-  copy_panel(h, h->P3, n, Y, ld, m, n);
-  if (R_out) {
-    // success: R = R2 R1 R0
-    GemmArgs a1 = G(n, n, n, R2, n, false, R1, n, false, Rt, n);
-    a1.cond = fail;
-    a1.cond_when = false;
-    gemm(h, a1);
-    GemmArgs a2 = G(n, n, n, Rt, n, false, R0, n, false, R_out, n);
-    a2.cond = fail;
-    a2.cond_when = false;
-    gemm(h, a2);
+  gemm(h, when_ok(G(m, n, n, Y, ld, false, Ri, n, false, Y, ld)));
+  if (R_out) {  // success: R = R2 R1 R0
+    gemm(h, when_ok(G(n, n, n, R2, n, false, R1, n, false, Rt, n)));
+    gemm(h, when_ok(G(n, n, n, Rt, n, false, R0, n, false, R_out, n)));
   }
-  // failure: TSQR of the pass-0 panel (= Y R0^-1), then R = R_tsqr R0
+  // failure in pass 1 or 2: factorise the pass-0 panel
+  hipLaunchKernelGGL(copy_panel_when_kernel, dim3(grid_for(m * n)), dim3(TPB), 0, st, h->P3,
+                     (int64_t)n, Y, ld, m, n, fail, 2, 3);
   tsqr(Y, m, n, ld, R_out ? Rt : nullptr, h->tsqr_ws, st, fail);
   if (R_out) {
     GemmArgs a3 = G(n, n, n, Rt, n, false, R0, n, false, R_out, n);
     a3.cond = fail;
     a3.cond_when = true;
-    gemm(h, a3);
+    gemm(h, a3);  // R = R_tsqr R0 (overwritten below when pass 0 failed)
+    hipLaunchKernelGGL(copy_panel_when_kernel, dim3(grid_for((int64_t)n * n)), dim3(TPB), 0, st,
+                       Rt, (int64_t)n, R_out, (int64_t)n, (int64_t)n, n, fail, 1, 1);
   }
 }
 

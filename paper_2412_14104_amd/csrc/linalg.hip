@@ -628,7 +628,7 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double*
   }
   __syncthreads();
   if (bad) {
-    if (tid == 0) *fail = 1;
+    if (tid == 0) *fail = pass + 1;  // which pass failed
     return;
   }
   if (q < n) {
