@@ -74,6 +74,30 @@ def cpu_baseline(chi, r, q, seed):
                       "are excluded, so this is an upper bound on the oracle's RG steps/s"}
 
 
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "contraction_gemm_bf16x3_chi32.md")
+KERNEL_SOURCE = os.path.join(HERE, "paper_2412_14104_amd", "csrc", "gemm_bf16x3.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the split contraction GEMM, from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes recorded in profiles/ (calibrated against a plain copy).  None unless
+    the summary was taken on the kernel source as it stands (its SHA-256 is recorded)."""
+    import hashlib
+    import re
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+        with open(KERNEL_SOURCE, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+source_sha256:\s*([0-9a-f]{64})",
+                  text)
+    if not m or m.group(2) != digest:
+        return None
+    return float(m.group(1))
+
+
 def run_path(pkg, torch, precision, chi, r, q, seed, beta, warmup, steps):
     """W untimed steps, then K steps timed with HIP events on the library's stream (bracketed
     by device synchronisation); returns the timing, the live contraction-GEMM timing and, for
@@ -160,6 +184,8 @@ def main():
     else:
         roofline = {"bound": "mfma", "achieved": alg, "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": alg / FP64_PEAK_TFLOPS, "traffic": None}
+    if split:
+        roofline["traffic"] = measured_traffic()
     roofline.update({"kernel": "contraction GEMMs (P = E.FM4 and Phi = Qt^T.P, both halves)",
                      "launches": launches, "flops_per_launch": main_run["flops_per_launch"],
                      "avg_launch_ms": avg_launch_s * 1e3})
