@@ -183,6 +183,19 @@ struct tatrg_handle {
   double *Smat;
   double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
   double *Ssq, *Usq, *Vsq, *Umat, *Vmat;
+  // Lanes: a stream of their own plus the scratch an independent chi^2-row RSVD needs, so the
+  // four isometry RSVDs (latency-bound chains of small factorisations) run concurrently.
+  struct Lane {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    double *Pb = nullptr, *P3 = nullptr, *Gq = nullptr, *tsqr_ws = nullptr, *partial = nullptr;
+    size_t partial_doubles = 0;
+    int* flag = nullptr;
+  };
+  static constexpr int N_LANES = 4;
+  Lane lane[N_LANES];
+  hipEvent_t fork = nullptr;
+  bool lanes = false;
 };
 
 namespace {
@@ -300,6 +313,16 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->Usq = cv.take(n2 * c); h->Vsq = cv.take(n2 * c);
   h->Umat = cv.take(n2 * c); h->Vmat = cv.take(n2 * c);
   h->small = nullptr;
+  for (int z = 0; z < tatrg_handle::N_LANES; ++z) {
+    tatrg_handle::Lane& ln = h->lane[z];
+    ln.Pb = cv.take(n2 * L);
+    ln.P3 = cv.take(n2 * L);
+    ln.Gq = cv.take(6 * (int64_t)MAX_W * MAX_W);
+    ln.tsqr_ws = cv.take(tsqr_ws_doubles(n2, (int)L));
+    ln.partial_doubles = (size_t)(8 * n2 * L);
+    ln.partial = cv.take(ln.partial_doubles);
+    ln.flag = (int*)cv.take(8);
+  }
 }
 
 bool hip_ok(tatrg_handle* h, const char* where) {
@@ -581,6 +604,36 @@ void pair_gram(tatrg_handle* h, const double* T1, const double* T2, double* out)
   gemm_long_k(h, G(d.n2, d.n2, d.n3, h->Ap, d.n3, false, rhs, d.n3, true, out, d.n2));
 }
 
+// While alive, the handle's stream and per-task scratch are those of a lane, so the stage
+// functions enqueue onto it unchanged.
+struct LaneScope {
+  tatrg_handle* h;
+  hipStream_t st;
+  double *P3, *Gq, *tsqr_ws, *partial;
+  size_t partial_doubles;
+  int* flag;
+  LaneScope(tatrg_handle* hh, const tatrg_handle::Lane& ln)
+      : h(hh), st(hh->st), P3(hh->P3), Gq(hh->Gq), tsqr_ws(hh->tsqr_ws), partial(hh->partial),
+        partial_doubles(hh->partial_doubles), flag(hh->flag) {
+    h->st = ln.st;
+    h->P3 = ln.P3;
+    h->Gq = ln.Gq;
+    h->tsqr_ws = ln.tsqr_ws;
+    h->partial = ln.partial;
+    h->partial_doubles = ln.partial_doubles;
+    h->flag = ln.flag;
+  }
+  ~LaneScope() {
+    h->st = st;
+    h->P3 = P3;
+    h->Gq = Gq;
+    h->tsqr_ws = tsqr_ws;
+    h->partial = partial;
+    h->partial_doubles = partial_doubles;
+    h->flag = flag;
+  }
+};
+
 void isometries(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
@@ -606,15 +659,29 @@ void isometries(tatrg_handle* h) {
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rY, n2));
   gemm(h, G(d.n4, c, c, h->B, c, false, py, c, false, h->AP, c));
   pair_gram(h, h->B, h->AP, rD);
+  // the four range finders are independent: one lane each (fork and join by events)
   const uint32_t sites[4] = {SITE_ISO_A, SITE_ISO_X, SITE_ISO_Y, SITE_ISO_D};
+  if (h->lanes) hipEventRecord(h->fork, st);
   for (int z = 0; z < 4; ++z) {
     DenseOp op;
     op.h = h;
     op.M = h->rho + z * n2 * n2;
     op.n = n2;
     double* U = h->UZ + z * n2 * d.L;
-    rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, true);
+    if (h->lanes) {
+      tatrg_handle::Lane& ln = h->lane[z];
+      hipStreamWaitEvent(ln.st, h->fork, 0);
+      {
+        LaneScope scope(h, ln);
+        rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, ln.Pb, true, true);
+      }
+      hipEventRecord(ln.done, ln.st);
+    } else {
+      rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, true);
+    }
   }
+  if (h->lanes)
+    for (int z = 0; z < 4; ++z) hipStreamWaitEvent(st, h->lane[z].done, 0);
 }
 
 void triad(tatrg_handle* h) {
@@ -817,6 +884,14 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
   char* base = (char*)(((uintptr_t)d_ws + 255) & ~(uintptr_t)255);
   Carver cv{base};
   carve(h, cv);
+  // lane streams (default priority) and events; without them the stages run on `stream` alone
+  bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
+  for (int z = 0; ok && z < tatrg_handle::N_LANES; ++z) {
+    ok = hipStreamCreateWithFlags(&h->lane[z].st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&h->lane[z].done, hipEventDisableTiming) == hipSuccess;
+  }
+  h->lanes = ok;
+  (void)hipGetLastError();
   *out = h;
   return TATRG_OK;
 }
@@ -1046,6 +1121,14 @@ int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
 void tatrg_destroy(tatrg_handle* h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  for (int z = 0; z < tatrg_handle::N_LANES; ++z) {
+    if (h->lane[z].st) {
+      hipStreamSynchronize(h->lane[z].st);
+      hipStreamDestroy(h->lane[z].st);
+    }
+    if (h->lane[z].done) hipEventDestroy(h->lane[z].done);
+  }
+  if (h->fork) hipEventDestroy(h->fork);
   delete h;
 }
 
