@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <memory>
 #include <vector>
 
 namespace tatrg {
@@ -191,6 +192,10 @@ struct tatrg_handle {
     double *Pb = nullptr, *P3 = nullptr, *Gq = nullptr, *tsqr_ws = nullptr, *partial = nullptr;
     size_t partial_doubles = 0;
     int* flag = nullptr;
+    // squeezer RSVD and its factors (chi^2-row panels, w x w core, chi-column factors)
+    double *Pa = nullptr, *Cm = nullptr, *RbT = nullptr, *Rb = nullptr, *Uh = nullptr;
+    double *Sh = nullptr, *Vh = nullptr, *Usq = nullptr, *Vsq = nullptr, *Umat = nullptr;
+    double *Vmat = nullptr, *probe = nullptr, *Pm = nullptr, *Oc = nullptr, *Dm = nullptr;
   };
   static constexpr int N_LANES = 4;
   Lane lane[N_LANES];
@@ -322,6 +327,16 @@ void carve(tatrg_handle* h, Carver& cv) {
     ln.partial_doubles = (size_t)(8 * n2 * L);
     ln.partial = cv.take(ln.partial_doubles);
     ln.flag = (int*)cv.take(8);
+    const int64_t ww = L;
+    ln.Pa = cv.take(n2 * ww);
+    ln.Cm = cv.take(n2 * n2);
+    ln.RbT = cv.take(ww * ww); ln.Rb = cv.take(ww * ww);
+    ln.Uh = cv.take(ww * ww); ln.Sh = cv.take(ww); ln.Vh = cv.take(ww * ww);
+    ln.Usq = cv.take(n2 * c); ln.Vsq = cv.take(n2 * c);
+    ln.Umat = cv.take(n2 * c); ln.Vmat = cv.take(n2 * c);
+    ln.probe = cv.take((int64_t)N_PROBES * n2);
+    ln.Pm = cv.take((int64_t)N_PROBES * ww);
+    ln.Oc = cv.take(ww * ww); ln.Dm = cv.take(ww);
   }
 }
 
@@ -608,29 +623,28 @@ void pair_gram(tatrg_handle* h, const double* T1, const double* T2, double* out)
 // functions enqueue onto it unchanged.
 struct LaneScope {
   tatrg_handle* h;
-  hipStream_t st;
-  double *P3, *Gq, *tsqr_ws, *partial;
-  size_t partial_doubles;
-  int* flag;
-  LaneScope(tatrg_handle* hh, const tatrg_handle::Lane& ln)
-      : h(hh), st(hh->st), P3(hh->P3), Gq(hh->Gq), tsqr_ws(hh->tsqr_ws), partial(hh->partial),
-        partial_doubles(hh->partial_doubles), flag(hh->flag) {
-    h->st = ln.st;
-    h->P3 = ln.P3;
-    h->Gq = ln.Gq;
-    h->tsqr_ws = ln.tsqr_ws;
-    h->partial = ln.partial;
-    h->partial_doubles = ln.partial_doubles;
-    h->flag = ln.flag;
+  tatrg_handle saved;  // the swapped fields of the handle (copied back on exit)
+  LaneScope(tatrg_handle* hh, const tatrg_handle::Lane& ln) : h(hh) {
+    saved.st = h->st; saved.P3 = h->P3; saved.Gq = h->Gq; saved.tsqr_ws = h->tsqr_ws;
+    saved.partial = h->partial; saved.partial_doubles = h->partial_doubles;
+    saved.flag = h->flag; saved.P1 = h->P1; saved.P2 = h->P2; saved.Cm = h->Cm;
+    saved.RbT = h->RbT; saved.Rb = h->Rb; saved.Uh = h->Uh; saved.Sh = h->Sh; saved.Vh = h->Vh;
+    saved.Usq = h->Usq; saved.Vsq = h->Vsq; saved.Umat = h->Umat; saved.Vmat = h->Vmat;
+    saved.probe = h->probe; saved.Pm = h->Pm; saved.Oc = h->Oc; saved.Dm = h->Dm;
+    h->st = ln.st; h->P3 = ln.P3; h->Gq = ln.Gq; h->tsqr_ws = ln.tsqr_ws;
+    h->partial = ln.partial; h->partial_doubles = ln.partial_doubles;
+    h->flag = ln.flag; h->P1 = ln.Pb; h->P2 = ln.Pa; h->Cm = ln.Cm;
+    h->RbT = ln.RbT; h->Rb = ln.Rb; h->Uh = ln.Uh; h->Sh = ln.Sh; h->Vh = ln.Vh;
+    h->Usq = ln.Usq; h->Vsq = ln.Vsq; h->Umat = ln.Umat; h->Vmat = ln.Vmat;
+    h->probe = ln.probe; h->Pm = ln.Pm; h->Oc = ln.Oc; h->Dm = ln.Dm;
   }
   ~LaneScope() {
-    h->st = st;
-    h->P3 = P3;
-    h->Gq = Gq;
-    h->tsqr_ws = tsqr_ws;
-    h->partial = partial;
-    h->partial_doubles = partial_doubles;
-    h->flag = flag;
+    h->st = saved.st; h->P3 = saved.P3; h->Gq = saved.Gq; h->tsqr_ws = saved.tsqr_ws;
+    h->partial = saved.partial; h->partial_doubles = saved.partial_doubles;
+    h->flag = saved.flag; h->P1 = saved.P1; h->P2 = saved.P2; h->Cm = saved.Cm;
+    h->RbT = saved.RbT; h->Rb = saved.Rb; h->Uh = saved.Uh; h->Sh = saved.Sh; h->Vh = saved.Vh;
+    h->Usq = saved.Usq; h->Vsq = saved.Vsq; h->Umat = saved.Umat; h->Vmat = saved.Vmat;
+    h->probe = saved.probe; h->Pm = saved.Pm; h->Oc = saved.Oc; h->Dm = saved.Dm;
   }
 };
 
@@ -759,42 +773,53 @@ void squeezers(tatrg_handle* h, double* rec) {
   cholesky_shifted(h->chol, (int)n2, 6, CHOL_SHIFT, h->flag, st);
   const uint32_t sq_sites[3] = {SITE_SQZ_2, SITE_SQZ_3, SITE_SQZ_4};
   const uint32_t pr_sites[3] = {SITE_PROBE_SQZ_2, SITE_PROBE_SQZ_3, SITE_PROBE_SQZ_4};
+  // the three squeezer pairs are independent after the Cholesky factors: one lane each
+  if (h->lanes) hipEventRecord(h->fork, st);
   for (int mi = 0; mi < 3; ++mi) {
-    const double* Ll = h->chol + mi * n2 * n2;        // rho_L + shift = Ll Ll^T, R_L = Ll^T
-    const double* Lr = h->chol + (3 + mi) * n2 * n2;  // R_R = Lr^T
-    // C = R_L R_R^T = Ll^T Lr
-    gemm(h, G(n2, n2, n2, Ll, n2, true, Lr, n2, false, h->Cm, n2));
-    DenseOp op;
-    op.h = h;
-    op.M = h->Cm;
-    op.n = n2;
-    const int w = d.L;
-    rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false, true);
-    // U = Q Uh[:, :c], V = Qb Vh[:, :c]
-    gemm(h, G(n2, c, w, h->P2, w, false, h->Uh, w, false, h->Usq, c));
-    gemm(h, G(n2, c, w, h->P1, w, false, h->Vh, w, false, h->Vsq, c));
-    double* S = h->Ssq + mi * c;
-    hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, S, h->Sh, (int)c);
-    if (rec)
-      hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec + mi * c, h->Sh,
-                         (int)c);
-    philox_gaussian(h->probe, N_PROBES, n2, n2, false, h->cfg.seed, (uint32_t)h->step,
-                    pr_sites[mi], st);
-    gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
-    gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, st);
-    hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, st, S, h->Dm, (int)c, SQZ_CUTOFF);
-    // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
-    // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
-    double* M = h->Msq + mi * n2 * c;
-    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
-    scale_cols(h->Vmat, h->Dm, n2, c, c, st);
-    gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
-    // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
-    gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
-    scale_cols(h->Umat, h->Dm, n2, c, c, st);
-    gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
-    transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, st);
+    if (h->lanes) hipStreamWaitEvent(h->lane[mi].st, h->fork, 0);
+    {
+      std::unique_ptr<LaneScope> scope;
+      if (h->lanes) scope.reset(new LaneScope(h, h->lane[mi]));
+      hipStream_t ls = h->st;
+      const double* Ll = h->chol + mi * n2 * n2;        // rho_L + shift = Ll Ll^T, R_L = Ll^T
+      const double* Lr = h->chol + (3 + mi) * n2 * n2;  // R_R = Lr^T
+      // C = R_L R_R^T = Ll^T Lr
+      gemm(h, G(n2, n2, n2, Ll, n2, true, Lr, n2, false, h->Cm, n2));
+      DenseOp op;
+      op.h = h;
+      op.M = h->Cm;
+      op.n = n2;
+      const int w = d.L;
+      rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false, true);
+      // U = Q Uh[:, :c], V = Qb Vh[:, :c]
+      gemm(h, G(n2, c, w, h->P2, w, false, h->Uh, w, false, h->Usq, c));
+      gemm(h, G(n2, c, w, h->P1, w, false, h->Vh, w, false, h->Vsq, c));
+      double* S = h->Ssq + mi * c;
+      hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, ls, S, h->Sh, (int)c);
+      if (rec)
+        hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, ls, rec + mi * c, h->Sh,
+                           (int)c);
+      philox_gaussian(h->probe, N_PROBES, n2, n2, false, h->cfg.seed, (uint32_t)h->step,
+                      pr_sites[mi], ls);
+      gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
+      gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, ls);
+      hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, ls, S, h->Dm, (int)c, SQZ_CUTOFF);
+      // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
+      // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
+      double* M = h->Msq + mi * n2 * c;
+      gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
+      scale_cols(h->Vmat, h->Dm, n2, c, c, ls);
+      gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
+      // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
+      gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
+      scale_cols(h->Umat, h->Dm, n2, c, c, ls);
+      gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
+      transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, ls);
+    }
+    if (h->lanes) hipEventRecord(h->lane[mi].done, h->lane[mi].st);
   }
+  if (h->lanes)
+    for (int mi = 0; mi < 3; ++mi) hipStreamWaitEvent(st, h->lane[mi].done, 0);
 }
 
 // One half of the contraction (Eqs. (makeMG) / (makeMH)):
