@@ -404,6 +404,26 @@ def rotate(t):
     return np.ascontiguousarray(t.transpose(1, 2, 3, 0, 4))
 
 
+# --------------------------------------------------------------------------- order parameter
+def open_slot(m):
+    """Slot that holds physical direction 4 after m steps: the slots rotate cyclically, so
+    after m steps slot j holds direction (j + m) mod 4 (0-based).  READING: the open leg of
+    X^(m) is the fourth direction of the lattice, wherever the rotation has put it."""
+    return (3 - m) % 4
+
+
+def order_parameter(phi, psi, m):
+    """X^(m) = (Tr A)^2 / Tr(A^2) with A_kl = sum_{i1,i2,i3} T_{i1 i2 i3 k, i1 i2 i3 l}
+    (Section 3, the order parameter used for the transition point): forward and backward legs
+    of three directions are identified and summed, the fourth stays open.  T = sum_g
+    Phi[f, g] Psi[b, g] is the m-th coarse tensor; X does not depend on its normalisation."""
+    j = open_slot(m)
+    ph = np.moveaxis(phi, j, 3)      # open leg to slot 4, the other three keep their order
+    ps = np.moveaxis(psi, j, 3)
+    a = np.einsum("xyzkg,xyzlg->kl", ph, ps)
+    return float(np.trace(a) ** 2 / np.trace(a @ a))
+
+
 # --------------------------------------------------------------------------- driver
 def widths(chi, r):
     """Internal-line (isometry / squeezer sketch) width L and swap sketch width Ls."""
@@ -414,13 +434,14 @@ def step(phi, psi, k, chi, r, q, seed):
     """One coarse-graining step along slot 1 (Section 2 and Fig. 3 flow): canonical form,
     bond swap, isometries, triad tensors, squeezers, contraction, slot rotation."""
     lw, ls = widths(chi, r)
+    x_m = order_parameter(phi, psi, k)
     a, s, b, c, smat = canonicalize(phi, psi, seed, k)
     x, sig, y = bond_swap(a, smat, b, ls, q, seed, k)
     iso = isometries(a, x, sig, y, b, lw, q, seed, k)
     e, f, g, h, ua, ux, uy, ud = triad(a, x, sig, y, b, iso)
     sq = squeezers(e, f, g, h, ua, ux, uy, ud, lw, q, seed, k)
     phi, psi = contract(e, f, g, h, ua, ux, uy, ud, sq)
-    info = {"lnc": math.log(c), "s": s, "sigma": sig,
+    info = {"lnc": math.log(c), "X": x_m, "s": s, "sigma": sig,
             "sqz": {mu: sq[mu][2] for mu in (2, 3, 4)}}
     return rotate(phi), rotate(psi), info
 
@@ -451,13 +472,15 @@ def run(beta, chi, r, q, seed, n_steps, w=None, record=True):
         if record:
             steps.append(info)
         else:
-            steps.append({"lnc": info["lnc"]})
+            steps.append({"lnc": info["lnc"], "X": info["X"]})
+    x_n = order_parameter(phi, psi, n_steps)
     lnc_n, ttr = finish(phi, psi, seed, n_steps)
     if not ttr > 0.0:
         raise FloatingPointError("non-positive trace of the final tensor")
     lnzv = acc + 2.0 ** (-n_steps) * (lnc_n + math.log(ttr))
     f = -lnzv / beta if beta > 0 else float("nan")
-    return {"lnZV": lnzv, "f": f, "steps": steps, "lnc_final": lnc_n, "ttr": ttr}
+    return {"lnZV": lnzv, "f": f, "steps": steps, "lnc_final": lnc_n, "ttr": ttr,
+            "X_final": x_n}
 
 
 def run_partial(beta, chi, r, q, seed, n_steps, w=None):

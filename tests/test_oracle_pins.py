@@ -326,3 +326,53 @@ def test_high_temperature_series():
         r = t.run(beta, 6, 2, 2, 0, 16)
         tt = math.tanh(beta)
         assert abs(r["lnZV"] - bf.high_t_series(beta)) < 6 * tt ** 4
+
+
+# ----------------------------------------------------------------------------- order parameter
+@pytest.mark.parametrize("beta", [0.0, 0.1, BETA_C, 0.4, 2.0])
+def test_order_parameter_of_the_initial_tensor_in_closed_form(beta):
+    """The initial tensor traced over three directions is A = 2 e^{3b} diag(cosh b, sinh b)
+    (each closed leg contributes sum_i W[a, i]^2 = e^b), so X^(0) = e^{2b} / cosh 2b."""
+    phi, psi = t.initial_state(beta, 4)
+    x = t.order_parameter(phi, psi, 0)
+    assert abs(x - math.exp(2 * beta) / math.cosh(2 * beta)) < 1e-14
+
+
+@pytest.mark.parametrize("beta", [0.15, BETA_C, 0.4])
+def test_order_parameter_after_exact_steps_is_a_ratio_of_partition_functions(beta):
+    """Untruncated steps keep T exact up to leg gauges, which X does not see.  Tr A^(m) is Z of
+    the m-step block with direction 4 closed on itself and Tr (A^(m))^2 is Z of two blocks
+    stacked along direction 4, so X^(m) = Z(e)^2 / Z(e1, e2, e3, 2 e4) by enumeration."""
+    r = t.run(beta, 16, 2, 2, 0, 2)
+    xs = [st["X"] for st in r["steps"]] + [r["X_final"]]
+    blocks = {0: (1, 1, 1, 1), 1: (2, 1, 1, 1), 2: (2, 2, 1, 1)}
+    for m, e in blocks.items():
+        lz1 = bf.ising_lnz_bruteforce(beta, e)
+        lz2 = bf.ising_lnz_bruteforce(beta, e[:3] + (2 * e[3],))
+        assert abs(xs[m] - math.exp(2 * lz1 - lz2)) < 1e-12, m
+
+
+def test_order_parameter_is_one_at_infinite_temperature():
+    """At beta = 0 every coarse tensor has rank one, and so has A: (Tr A)^2 = Tr A^2."""
+    r = t.run(0.0, 6, 2, 2, 0, 8)
+    for x in [st["X"] for st in r["steps"]] + [r["X_final"]]:
+        assert abs(x - 1.0) < 1e-13
+
+
+def test_order_parameter_counts_two_ground_states_at_low_temperature():
+    """Deep in the ordered phase a block has two degenerate ground states: X -> 2.  A single
+    flipped boundary spin costs exp(-4 beta) on the one- and two-site blocks; from the
+    four-site block on the gap is large enough that X = 2 to rounding."""
+    beta = 3.0
+    r = t.run(beta, 6, 2, 2, 0, 16)
+    xs = [st["X"] for st in r["steps"]] + [r["X_final"]]
+    for m, x in enumerate(xs):
+        assert abs(x - 2.0) < (8 * math.exp(-4 * beta) if m < 2 else 1e-12), m
+
+
+def test_order_parameter_separates_the_phases():
+    """Sanity only: on the isotropic 2^8-site block (m = 8), far from the transition
+    (beta_c ~ 0.1497), X is near the disordered (1) or ordered (2) fixed point."""
+    lo = t.run(0.10, 6, 2, 2, 0, 8)["X_final"]
+    hi = t.run(0.20, 6, 2, 2, 0, 8)["X_final"]
+    assert abs(lo - 1.0) < 0.15 and abs(hi - 2.0) < 0.05
