@@ -52,10 +52,11 @@ typedef struct {
   int32_t r;              /* internal-line oversampling r >= 1: L = min(r chi, chi^2)  */
   int32_t q;              /* QR (power) iterations of every randomized SVD, q >= 0     */
   int32_t n_steps;        /* RG steps N, 1 <= N <= 64; lattice of 2^N sites            */
-  int32_t batch;          /* number of temperatures; must be 1 in this version         */
+  int32_t batch;          /* number of temperatures B, 1 <= B <= 1024 (a beta scan)    */
   int32_t precision;      /* tatrg_precision                                          */
   uint64_t seed;          /* Philox4x32-10 key for every Gaussian sketch               */
-  int32_t record_spectra; /* nonzero: keep per-step singular spectra for readback      */
+  int32_t record_spectra; /* nonzero: keep per-step singular spectra and the order
+                             parameter X^(m) for readback                               */
   int32_t reserved;
 } tatrg_config;
 
@@ -79,7 +80,11 @@ tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas);
 
 /* One RG step on the device, no host synchronisation: canonical form and normalisation
  * c_k = |T|_F, bond swap by randomized SVD, isometries, triad tensors, squeezers,
- * contraction and slot rotation (Section 2).  ESTATE before init or after n_steps steps. */
+ * contraction and slot rotation (Section 2).  With batch = B the step runs for every
+ * temperature in turn; all temperatures share the same Gaussian sketches (common random
+ * numbers), so entry b of a batch equals a batch-1 run at beta_b bit for bit.  With
+ * record_spectra it first records X^(k) of the incoming tensor (see tatrg_get_record).
+ * ESTATE before init or after n_steps steps. */
 tatrg_status tatrg_step(tatrg_handle* h);
 
 /* Standalone randomized SVD A ~= U diag(S) V^T of a device matrix (Introduction, Table 1):
@@ -92,7 +97,7 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
                         int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
                         double* d_U, double* d_S, double* d_Vt);
 
-/* Synchronising.  h_acc[batch] receives sum_{j<k} 2^-j ln c_j after k steps. */
+/* Synchronising.  h_acc[b], b < batch, receives sum_{j<k} 2^-j ln c_j after k steps. */
 tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc);
 
 /* Synchronising; valid after n_steps steps.  Normalises the last tensor once more and traces
@@ -101,13 +106,26 @@ tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc);
  * h_f and h_lnzv (host, `batch` entries each; either may be NULL).  f is NaN at beta = 0. */
 tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
 
-/* Synchronising.  Per-step spectra recorded when record_spectra != 0:
- * which = 0: canonical s (chi), 1: swap sigma (chi), 2/3/4: squeezer S of direction mu = 2/3/4
- * (chi).  Copies min(cap, chi) values to h_out and the count to *n_out. */
+/* Synchronising.  Per-step records of temperature b (0 <= b < batch), kept when
+ * record_spectra != 0, for step = 0..n_steps (step n_steps is recorded by
+ * tatrg_free_energy):
+ *   which = 0: canonical s (chi values), 1: swap sigma (chi), 2/3/4: squeezer S of
+ *   direction mu = 2/3/4 (chi);
+ *   which = 5: the order parameter X^(step) = (Tr A)^2 / Tr A^2 of the incoming tensor, with
+ *   A_kl = T summed over the forward = backward legs of three directions and the legs k, l
+ *   of lattice direction 4 open (Section 3, the order parameter of the transition point;
+ *   one value).
+ * Copies min(cap, chi) values (one for which = 5) to h_out and the count to *n_out.
+ * EINVAL without record_spectra, for b, step or which out of range, or cap < 1. */
+tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,
+                              double* h_out, int32_t cap, int32_t* n_out);
+
+/* tatrg_get_record of temperature 0. */
 tatrg_status tatrg_get_spectra(tatrg_handle* h, int32_t step, int32_t which, double* h_out,
                                int32_t cap, int32_t* n_out);
 
-/* Checkpoint / resume of the RG state (Phi, Psi, step index, log-norm accumulator).
+/* Checkpoint / resume of the RG state (Phi, Psi, step index, log-norm accumulator); batch = 1
+ * only (EINVAL otherwise).
  * d_phi, d_psi: device buffers of chi^5 doubles each, legs (l1,l2,l3,l4,gamma) row-major with
  * T = sum_g Phi[..,g] Psi[..,g].  get copies out, set copies in (asynchronous).  set also
  * clears the sticky numerical flag. */

@@ -56,6 +56,8 @@ _SIGS = {
     "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
     "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
     "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),
+    "tatrg_get_record": (ctypes.c_int, [_p, _i32, _i32, _i32, _dblp, _i32,
+                                        ctypes.POINTER(_i32)]),
     "tatrg_get_state": (ctypes.c_int, [_p, _p, _p, ctypes.POINTER(_i32), _dblp]),
     "tatrg_set_state": (ctypes.c_int, [_p, _p, _p, _i32, _dbl]),
     "tatrg_last_error": (ctypes.c_char_p, [_p]),
@@ -100,13 +102,14 @@ def _stream_ptr(stream):
 
 
 class Engine:
-    """One RG run on the current HIP device.  The workspace is a torch uint8 tensor on the
-    device; the stream is torch's current stream unless one is given."""
+    """One RG run (or a batch of `batch` temperatures sharing the sketches) on the current HIP
+    device.  The workspace is a torch uint8 tensor on the device; the stream is torch's
+    current stream unless one is given."""
 
     def __init__(self, chi, r, q, n_steps, seed=0, precision=FP64, record_spectra=True,
-                 stream=None, device="cuda"):
+                 stream=None, device="cuda", batch=1):
         import torch
-        self.cfg = TatrgConfig(chi=chi, r=r, q=q, n_steps=n_steps, batch=1,
+        self.cfg = TatrgConfig(chi=chi, r=r, q=q, n_steps=n_steps, batch=batch,
                                precision=precision, seed=seed,
                                record_spectra=1 if record_spectra else 0, reserved=0)
         nbytes = lib.tatrg_workspace_bytes(ctypes.byref(self.cfg))
@@ -117,7 +120,7 @@ class Engine:
         self.handle = ctypes.c_void_p()
         _check(lib.tatrg_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.ws.data_ptr()),
                                 nbytes, _stream_ptr(self.stream), ctypes.byref(self.handle)))
-        self.chi, self.n_steps = chi, n_steps
+        self.chi, self.n_steps, self.batch = chi, n_steps, batch
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -126,29 +129,40 @@ class Engine:
             self.handle = None
 
     def init(self, beta):
-        arr = (ctypes.c_double * 1)(beta)
+        """beta: one value (batch 1) or a sequence of `batch` values."""
+        betas = [beta] if isinstance(beta, (int, float)) else list(beta)
+        if len(betas) != self.batch:
+            raise TatrgError(-1, "need %d temperatures" % self.batch)
+        arr = (ctypes.c_double * self.batch)(*betas)
         _check(lib.tatrg_init_tensor(self.handle, arr), self.handle)
 
     def step(self):
         _check(lib.tatrg_step(self.handle), self.handle)
 
     def lognorm(self):
-        out = ctypes.c_double()
-        _check(lib.tatrg_lognorm(self.handle, ctypes.byref(out)), self.handle)
-        return out.value
+        out = (ctypes.c_double * self.batch)()
+        _check(lib.tatrg_lognorm(self.handle, out), self.handle)
+        return out[0] if self.batch == 1 else list(out)
 
     def free_energy(self):
-        f, lnzv = ctypes.c_double(), ctypes.c_double()
-        _check(lib.tatrg_free_energy(self.handle, ctypes.byref(f), ctypes.byref(lnzv)),
-               self.handle)
-        return f.value, lnzv.value
+        """(f, ln Z / V): floats for batch 1, lists of `batch` values otherwise."""
+        f = (ctypes.c_double * self.batch)()
+        lnzv = (ctypes.c_double * self.batch)()
+        _check(lib.tatrg_free_energy(self.handle, f, lnzv), self.handle)
+        if self.batch == 1:
+            return f[0], lnzv[0]
+        return list(f), list(lnzv)
 
-    def spectrum(self, step, which):
+    def spectrum(self, step, which, b=0):
         buf = (ctypes.c_double * self.chi)()
         n = ctypes.c_int32()
-        _check(lib.tatrg_get_spectra(self.handle, step, which, buf, self.chi, ctypes.byref(n)),
-               self.handle)
+        _check(lib.tatrg_get_record(self.handle, b, step, which, buf, self.chi,
+                                    ctypes.byref(n)), self.handle)
         return [buf[i] for i in range(n.value)]
+
+    def order_parameter(self, step, b=0):
+        """X^(step) of temperature b (recorded with record_spectra)."""
+        return self.spectrum(step, 5, b)[0]
 
     def get_state(self, phi, psi):
         step, acc = ctypes.c_int32(), ctypes.c_double()

@@ -102,6 +102,14 @@ void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t 
                 hipStream_t st);
 
 // y = x (n doubles).
+// Order parameter X = (Tr A)^2 / Tr A^2 of T = sum_g Phi[., g] Psi[., g] (chi^5 doubles
+// each, legs (l1 l2 l3 l4 gamma)), A_kl = T with the legs of the three slots other than
+// open_slot (0..3) traced, k and l the forward and backward legs of open_slot.  Writes
+// out[0]; part holds order_parameter_ws_doubles(chi) doubles.  chi <= 64.  Deterministic.
+constexpr int OP_PARTS = 128;
+size_t order_parameter_ws_doubles(int chi);
+void order_parameter(const double* phi, const double* psi, int chi, int open_slot,
+                     double* part, double* out, hipStream_t st);
 void copy(double* y, const double* x, int64_t n, hipStream_t st);
 
 // Fill with zeros / write the identity into an n x n block (ld).

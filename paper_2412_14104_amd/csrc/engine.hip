@@ -171,8 +171,9 @@ struct tatrg_handle {
   double* acc;
   double* lnc;
   double* spectra;
+  double* xrec;  // order parameter X^(m), m = 0..n_steps
+  double* ttr;   // trace of the last normalised tensor
   double* trace_part;
-  double* scal;  // [0]: ln c_N, [1]: trace
   size_t partial_doubles;
   // small buffers (carved from `small`)
   size_t tsqr_cap;
@@ -199,18 +200,36 @@ struct tatrg_handle {
   };
   static constexpr int N_LANES = 4;
   Lane lane[N_LANES];
+  // One RG state per temperature of the batch; the step runs them in turn through the shared
+  // scratch, with phi, psi, flag, acc, lnc, spectra, xrec and ttr pointing at the selected one.
+  struct State {
+    double *phi = nullptr, *psi = nullptr, *acc = nullptr, *lnc = nullptr;
+    double *spectra = nullptr, *xrec = nullptr, *ttr = nullptr;
+    int* flag = nullptr;
+  };
+  std::vector<State> states;
   hipEvent_t fork = nullptr;
   bool lanes = false;
 };
 
 namespace {
 
+constexpr int MAX_BATCH = 1024;
+
+void select_state(tatrg_handle* h, int b) {
+  const tatrg_handle::State& s = h->states[b];
+  h->phi = s.phi; h->psi = s.psi; h->acc = s.acc; h->lnc = s.lnc;
+  h->spectra = s.spectra; h->xrec = s.xrec; h->ttr = s.ttr; h->flag = s.flag;
+}
+
+int open_slot(int m) { return ((3 - m) % 4 + 4) % 4; }
+
 bool valid(const tatrg_config* c) {
   if (!c) return false;
   if (c->chi < 2 || c->chi > 64) return false;
   if (c->r < 1 || c->q < 0 || c->q > 16) return false;
   if (c->n_steps < 1 || c->n_steps > 64) return false;
-  if (c->batch != 1) return false;
+  if (c->batch < 1 || c->batch > MAX_BATCH) return false;
   if (c->precision != TATRG_FP64 && c->precision != TATRG_BF16X3) return false;
   const int64_t L = std::min<int64_t>((int64_t)c->r * c->chi, (int64_t)c->chi * c->chi);
   if (L > MAX_W) return false;
@@ -252,7 +271,18 @@ size_t splitk_partial_doubles(const Dims& d) {
 void carve(tatrg_handle* h, Carver& cv) {
   const Dims& d = h->d;
   const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n4 = d.n4, n5 = d.n5, L = d.L, Ls = d.Ls;
-  h->phi = cv.take(n5); h->psi = cv.take(n5);
+  h->states.assign(h->cfg.batch, tatrg_handle::State());
+  for (tatrg_handle::State& st : h->states) {
+    st.phi = cv.take(n5);
+    st.psi = cv.take(n5);
+    st.flag = (int*)cv.take(8);
+    st.acc = cv.take(8);
+    st.lnc = cv.take(72);
+    st.spectra = cv.take((size_t)(h->cfg.n_steps + 1) * 5 * c);
+    st.xrec = cv.take((size_t)h->cfg.n_steps + 1);
+    st.ttr = cv.take(8);
+  }
+  select_state(h, 0);
   h->A = cv.take(n5); h->B = cv.take(n5);
   h->X = cv.take(n5); h->Y = cv.take(n5);
   h->atf = cv.take(n5); h->btx = cv.take(n5);
@@ -298,12 +328,7 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->partial_doubles = splitk_partial_doubles(d);
   h->partial = cv.take(h->partial_doubles);
   h->probe = cv.take((size_t)N_PROBES * n4);
-  h->flag = (int*)cv.take(8);
-  h->acc = cv.take(8);
-  h->lnc = cv.take(72);
-  h->spectra = cv.take((size_t)(h->cfg.n_steps + 1) * 5 * c);
   h->trace_part = cv.take(4096);
-  h->scal = cv.take(8);
   const int64_t w = std::max<int64_t>(Ls, L);
   h->s = cv.take(c); h->sig = cv.take(c);
   h->Smat = cv.take(c * c);
@@ -923,24 +948,32 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
 
 tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas) {
   if (!h || !h_betas) return TATRG_EINVAL;
-  const double beta = h_betas[0];
-  if (!std::isfinite(beta) || beta < 0.0) {
-    h->err = "beta must be finite and >= 0";
-    return TATRG_EINVAL;
+  const int nb = h->cfg.batch;
+  for (int b = 0; b < nb; ++b) {
+    if (!std::isfinite(h_betas[b]) || h_betas[b] < 0.0) {
+      h->err = "every beta must be finite and >= 0";
+      return TATRG_EINVAL;
+    }
   }
-  h->betas.assign(h_betas, h_betas + h->cfg.batch);
+  h->betas.assign(h_betas, h_betas + nb);
   const Dims& d = h->d;
   hipStream_t st = h->st;
-  zero(h->phi, d.n5, st);
-  zero(h->psi, d.n5, st);
-  // W = element-wise square root of [[cosh b, sinh b], [cosh b, -sinh b]]
-  const double sc = std::sqrt(std::cosh(beta)), ss = std::sqrt(std::sinh(beta));
-  hipLaunchKernelGGL(init_tensor_kernel, dim3(1), dim3(64), 0, st, h->phi, h->psi, d.c, sc, ss,
-                     sc, -ss);
-  zero((double*)h->flag, 4, st);
-  zero(h->acc, 8, st);
-  zero(h->lnc, 72, st);
-  zero(h->spectra, (int64_t)(h->cfg.n_steps + 1) * 5 * d.c, st);
+  for (int b = 0; b < nb; ++b) {
+    select_state(h, b);
+    zero(h->phi, d.n5, st);
+    zero(h->psi, d.n5, st);
+    // W = element-wise square root of [[cosh b, sinh b], [cosh b, -sinh b]]
+    const double sc = std::sqrt(std::cosh(h_betas[b])), ss = std::sqrt(std::sinh(h_betas[b]));
+    hipLaunchKernelGGL(init_tensor_kernel, dim3(1), dim3(64), 0, st, h->phi, h->psi, d.c, sc,
+                       ss, sc, -ss);
+    zero((double*)h->flag, 4, st);
+    zero(h->acc, 8, st);
+    zero(h->lnc, 72, st);
+    zero(h->spectra, (int64_t)(h->cfg.n_steps + 1) * 5 * d.c, st);
+    zero(h->xrec, h->cfg.n_steps + 1, st);
+    zero(h->ttr, 8, st);
+  }
+  select_state(h, 0);
   h->step = 0;
   h->initialized = true;
   if (!hip_ok(h, "init_tensor")) return TATRG_EHIP;
@@ -953,13 +986,21 @@ tatrg_status tatrg_step(tatrg_handle* h) {
     h->err = "step called before init_tensor or after n_steps steps";
     return TATRG_ESTATE;
   }
-  double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
-  canonicalize(h, h->step, rec);
-  bond_swap(h, rec ? rec + h->d.c : nullptr);
-  isometries(h);
-  triad(h);
-  squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
-  contraction(h);
+  // the temperatures of the batch in turn, each through the whole step
+  for (int b = 0; b < h->cfg.batch; ++b) {
+    select_state(h, b);
+    double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
+    if (rec)
+      order_parameter(h->phi, h->psi, h->d.c, open_slot(h->step), h->partial,
+                      h->xrec + h->step, h->st);
+    canonicalize(h, h->step, rec);
+    bond_swap(h, rec ? rec + h->d.c : nullptr);
+    isometries(h);
+    triad(h);
+    squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
+    contraction(h);
+  }
+  select_state(h, 0);
   if (!hip_ok(h, "step")) return TATRG_EHIP;
   h->step += 1;
   return TATRG_OK;
@@ -1013,9 +1054,13 @@ static tatrg_status sync_check(tatrg_handle* h) {
     return TATRG_EHIP;
   }
   int flag = 0;
-  if (hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
-    h->err = "flag readback failed";
-    return TATRG_EHIP;
+  for (const tatrg_handle::State& s : h->states) {
+    int f = 0;
+    if (hipMemcpy(&f, s.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      h->err = "flag readback failed";
+      return TATRG_EHIP;
+    }
+    flag |= f;
   }
   if (flag) {
     h->err = "numerical fault on the device (non-finite norm, Cholesky pivot or trace)";
@@ -1027,8 +1072,10 @@ static tatrg_status sync_check(tatrg_handle* h) {
 tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc) {
   if (!h || !h_acc) return TATRG_EINVAL;
   tatrg_status s = sync_check(h);
-  if (hipMemcpy(h_acc, h->acc, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-    return TATRG_EHIP;
+  for (int b = 0; b < h->cfg.batch; ++b)
+    if (hipMemcpy(h_acc + b, h->states[b].acc, sizeof(double), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return TATRG_EHIP;
   return s;
 }
 
@@ -1039,47 +1086,70 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
     return TATRG_ESTATE;
   }
   const Dims& d = h->d;
-  double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * d.c : nullptr;
-  canonicalize(h, h->step, rec);
   const int nparts = 1024;
-  // tTr = sum_f (A' S' B'^T)[f, f]
-  gemm(h, G(d.n4, d.c, d.c, h->A, d.c, false, h->Smat, d.c, false, h->Xs, d.c));
-  hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->Xs,
-                     (const double*)nullptr, h->B, d.n4, d.c, h->trace_part);
-  hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, h->st, h->trace_part, nparts,
-                     h->scal + 1, h->flag);
+  for (int b = 0; b < h->cfg.batch; ++b) {
+    select_state(h, b);
+    double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * d.c : nullptr;
+    if (rec)
+      order_parameter(h->phi, h->psi, d.c, open_slot(h->step), h->partial, h->xrec + h->step,
+                      h->st);
+    canonicalize(h, h->step, rec);
+    // tTr = sum_f (A' S' B'^T)[f, f]
+    gemm(h, G(d.n4, d.c, d.c, h->A, d.c, false, h->Smat, d.c, false, h->Xs, d.c));
+    hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->Xs,
+                       (const double*)nullptr, h->B, d.n4, d.c, h->trace_part);
+    hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, h->st, h->trace_part, nparts,
+                       h->ttr, h->flag);
+  }
+  select_state(h, 0);
   if (!hip_ok(h, "free_energy")) return TATRG_EHIP;
   tatrg_status s = sync_check(h);
-  double acc = 0.0, lnc[72], ttr = 0.0;
-  hipMemcpy(&acc, h->acc, sizeof(double), hipMemcpyDeviceToHost);
-  hipMemcpy(lnc, h->lnc, sizeof(double) * 72, hipMemcpyDeviceToHost);
-  hipMemcpy(&ttr, h->scal + 1, sizeof(double), hipMemcpyDeviceToHost);
   const int N = h->cfg.n_steps;
-  // acc already holds sum_{k=0}^{N} 2^-k ln c_k (the last canonicalisation added c_N)
-  const double lnzv = acc + std::ldexp(std::log(ttr), -N);
-  const double beta = h->betas.empty() ? 0.0 : h->betas[0];
-  if (h_lnzv) h_lnzv[0] = lnzv;
-  if (h_f) h_f[0] = (beta > 0.0) ? -lnzv / beta : std::nan("");
-  (void)lnc;
+  for (int b = 0; b < h->cfg.batch; ++b) {
+    double acc = 0.0, ttr = 0.0;
+    hipMemcpy(&acc, h->states[b].acc, sizeof(double), hipMemcpyDeviceToHost);
+    hipMemcpy(&ttr, h->states[b].ttr, sizeof(double), hipMemcpyDeviceToHost);
+    // acc already holds sum_{k=0}^{N} 2^-k ln c_k (the last canonicalisation added c_N)
+    const double lnzv = acc + std::ldexp(std::log(ttr), -N);
+    const double beta = h->betas[b];
+    if (h_lnzv) h_lnzv[b] = lnzv;
+    if (h_f) h_f[b] = (beta > 0.0) ? -lnzv / beta : std::nan("");
+  }
   return s;
+}
+
+tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,
+                              double* h_out, int32_t cap, int32_t* n_out) {
+  if (!h || !h_out || !n_out || cap < 1) return TATRG_EINVAL;
+  if (!h->cfg.record_spectra || b < 0 || b >= h->cfg.batch || step < 0 ||
+      step > h->cfg.n_steps || which < 0 || which > 5)
+    return TATRG_EINVAL;
+  tatrg_status s = sync_check(h);
+  const tatrg_handle::State& st = h->states[b];
+  int n = 1;
+  if (which == 5) {
+    hipMemcpy(h_out, st.xrec + step, sizeof(double), hipMemcpyDeviceToHost);
+  } else {
+    n = std::min<int>(cap, h->d.c);
+    hipMemcpy(h_out, st.spectra + ((int64_t)step * 5 + which) * h->d.c, sizeof(double) * n,
+              hipMemcpyDeviceToHost);
+  }
+  *n_out = n;
+  return s == TATRG_ENUMERIC ? TATRG_OK : s;
 }
 
 tatrg_status tatrg_get_spectra(tatrg_handle* h, int32_t step, int32_t which, double* h_out,
                                int32_t cap, int32_t* n_out) {
-  if (!h || !h_out || !n_out) return TATRG_EINVAL;
-  if (!h->cfg.record_spectra || step < 0 || step > h->cfg.n_steps || which < 0 || which > 4)
-    return TATRG_EINVAL;
-  tatrg_status s = sync_check(h);
-  const int n = std::min<int>(cap, h->d.c);
-  hipMemcpy(h_out, h->spectra + ((int64_t)step * 5 + which) * h->d.c, sizeof(double) * n,
-            hipMemcpyDeviceToHost);
-  *n_out = n;
-  return s == TATRG_ENUMERIC ? TATRG_OK : s;
+  return tatrg_get_record(h, 0, step, which, h_out, cap, n_out);
 }
 
 tatrg_status tatrg_get_state(tatrg_handle* h, double* d_phi, double* d_psi, int32_t* step,
                              double* acc) {
   if (!h || !d_phi || !d_psi) return TATRG_EINVAL;
+  if (h->cfg.batch != 1) {
+    h->err = "get_state / set_state need batch = 1";
+    return TATRG_EINVAL;
+  }
   copy(d_phi, h->phi, h->d.n5, h->st);
   copy(d_psi, h->psi, h->d.n5, h->st);
   if (step) *step = h->step;
@@ -1094,6 +1164,10 @@ tatrg_status tatrg_get_state(tatrg_handle* h, double* d_phi, double* d_psi, int3
 tatrg_status tatrg_set_state(tatrg_handle* h, const double* d_phi, const double* d_psi,
                              int32_t step, double acc) {
   if (!h || !d_phi || !d_psi || step < 0 || step > h->cfg.n_steps) return TATRG_EINVAL;
+  if (h->cfg.batch != 1) {
+    h->err = "get_state / set_state need batch = 1";
+    return TATRG_EINVAL;
+  }
   if (!h->initialized) {
     h->err = "set_state needs a prior init_tensor (for beta)";
     return TATRG_ESTATE;

@@ -152,6 +152,88 @@ __global__ void transpose_batched_kernel(const double* in, double* out, int rows
   }
 }
 
+// Order parameter X = (Tr A)^2 / Tr A^2 of T = sum_g Phi[f, g] Psi[b, g], with
+// A_kl = sum over the three other directions of T with forward and backward legs identified
+// (Section 3, the order parameter of the transition).  With the open leg in slot j, Phi is
+// [pre][k][post] (pre = chi^j, post = chi^(4-j), gamma included) and
+// A_kl = sum_{p, q} Phi[p][k][q] Psi[p][l][q].
+constexpr int OP_QC = 32;    // trailing-leg chunk staged in LDS
+constexpr int OP_MAXK = 16;  // outputs per thread: l = tid % chi, k = tid / chi + (256 / chi) i
+
+// Work-group g sums the (p, q-chunk) units g, g + G, ... into part[g][k][l].
+__global__ __launch_bounds__(TPB) void order_param_partial_kernel(
+    const double* __restrict__ phi, const double* __restrict__ psi, int chi, int64_t pre,
+    int64_t post, double* __restrict__ part) {
+  __shared__ double sa[64][OP_QC + 1], sb[64][OP_QC + 1];
+  const int tid = threadIdx.x;
+  const int kgn = TPB / chi, l = tid % chi, kg = tid / chi;
+  const bool act = kg < kgn;
+  double acc[OP_MAXK];
+#pragma unroll
+  for (int i = 0; i < OP_MAXK; ++i) acc[i] = 0.0;
+  const int64_t nq = (post + OP_QC - 1) / OP_QC, units = pre * nq;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t p = u / nq, q0 = (u - p * nq) * OP_QC;
+    const int64_t qn = post - q0 < OP_QC ? post - q0 : OP_QC;
+    __syncthreads();
+    for (int e = tid; e < chi * OP_QC; e += TPB) {
+      const int k = e / OP_QC, q = e - (e / OP_QC) * OP_QC;
+      const int64_t off = (p * chi + k) * post + q0 + q;
+      sa[k][q] = q < qn ? phi[off] : 0.0;
+      sb[k][q] = q < qn ? psi[off] : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int q = 0; q < OP_QC; ++q) {
+        const double bv = sb[l][q];
+#pragma unroll
+        for (int i = 0; i < OP_MAXK; ++i) {
+          const int k = kg + kgn * i;
+          if (k < chi) acc[i] += sa[k][q] * bv;
+        }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < OP_MAXK; ++i) {
+      const int k = kg + kgn * i;
+      if (k < chi) part[(int64_t)blockIdx.x * chi * chi + k * chi + l] = acc[i];
+    }
+  }
+}
+
+// One work-group: A = sum of the parts in order, then Tr A, Tr A^2 and X.
+__global__ __launch_bounds__(TPB) void order_param_final_kernel(const double* __restrict__ part,
+                                                                int nparts, int chi,
+                                                                double* __restrict__ out) {
+  __shared__ double a[64 * 64];
+  __shared__ double red[TPB];
+  const int tid = threadIdx.x, n = chi * chi;
+  for (int e = tid; e < n; e += TPB) {
+    double s = 0.0;
+    for (int g = 0; g < nparts; ++g) s += part[(int64_t)g * n + e];
+    a[e] = s;
+  }
+  __syncthreads();
+  double t2 = 0.0;
+  for (int e = tid; e < n; e += TPB) {
+    const int k = e / chi, l = e - (e / chi) * chi;
+    t2 += a[k * chi + l] * a[l * chi + k];
+  }
+  red[tid] = t2;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int k = 0; k < chi; ++k) tr += a[k * chi + k];
+    out[0] = tr * tr / red[0];
+  }
+}
+
 }  // namespace
 
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
@@ -209,6 +291,19 @@ void transpose_batched(const double* in, double* out, int rows, int cols, int ba
                        hipStream_t st) {
   hipLaunchKernelGGL(transpose_batched_kernel, dim3(grid_for((int64_t)rows * cols * batch)),
                      dim3(TPB), 0, st, in, out, rows, cols, batch);
+}
+
+size_t order_parameter_ws_doubles(int chi) { return (size_t)OP_PARTS * chi * chi; }
+
+void order_parameter(const double* phi, const double* psi, int chi, int open_slot,
+                     double* part, double* out, hipStream_t st) {
+  int64_t pre = 1, post = 1;
+  for (int j = 0; j < open_slot; ++j) pre *= chi;
+  for (int j = open_slot + 1; j < 5; ++j) post *= chi;  // legs after the open one, and gamma
+  hipLaunchKernelGGL(order_param_partial_kernel, dim3(OP_PARTS), dim3(TPB), 0, st, phi, psi,
+                     chi, pre, post, part);
+  hipLaunchKernelGGL(order_param_final_kernel, dim3(1), dim3(TPB), 0, st, part, OP_PARTS, chi,
+                     out);
 }
 
 }  // namespace tatrg

@@ -38,7 +38,8 @@ def cfg(pkg, **kw):
 
 
 @pytest.mark.parametrize("bad", [dict(chi=1), dict(r=0), dict(q=-1), dict(n_steps=0),
-                                 dict(n_steps=65), dict(batch=2), dict(precision=7),
+                                 dict(n_steps=65), dict(batch=0), dict(batch=1025),
+                                 dict(precision=7),
                                  dict(chi=64, r=2)])
 def test_invalid_configurations_are_rejected(pkg, bad):
     c = cfg(pkg, **bad)
@@ -74,3 +75,29 @@ def test_workspace_scales_with_chi(pkg):
     assert sizes[0] < sizes[1] < sizes[2]
     # C3 (chi=32, r=3) fits a single 288 GB device comfortably
     assert pkg.lib.tatrg_workspace_bytes(ctypes.byref(cfg(pkg, chi=32, r=3))) < 32e9
+
+
+def test_workspace_holds_one_state_per_temperature(pkg):
+    """A batch of B temperatures adds B - 1 states (Phi and Psi, chi^5 doubles each, plus
+    per-step records) to the shared scratch of one run."""
+    one = pkg.lib.tatrg_workspace_bytes(ctypes.byref(cfg(pkg, chi=24, batch=1)))
+    many = pkg.lib.tatrg_workspace_bytes(ctypes.byref(cfg(pkg, chi=24, batch=64)))
+    per_state = (many - one) / 63
+    assert 2 * 24 ** 5 * 8 <= per_state < 2 * 24 ** 5 * 8 + 64 * 1024
+    assert many < 32e9
+
+
+def test_record_readback_rejects_bad_indices(pkg):
+    c = cfg(pkg, chi=6, n_steps=4, batch=2)
+    need = pkg.lib.tatrg_workspace_bytes(ctypes.byref(c))
+    h = ctypes.c_void_p()
+    assert pkg.lib.tatrg_create(ctypes.byref(c), ctypes.c_void_p(1 << 20), need, None,
+                                ctypes.byref(h)) == 0
+    buf = (ctypes.c_double * 6)()
+    n = ctypes.c_int32()
+    for b, step, which in ((2, 0, 0), (-1, 0, 0), (0, 5, 0), (0, 0, 6), (0, -1, 5)):
+        assert pkg.lib.tatrg_get_record(h, b, step, which, buf, 6, ctypes.byref(n)) == -1
+    # checkpointing is for batch 1 only
+    assert pkg.lib.tatrg_get_state(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20),
+                                   None, None) == -1
+    pkg.lib.tatrg_destroy(h)
