@@ -10,13 +10,14 @@
 // share a second set flushed every LO_FLUSH_TILES steps.
 //
 // Layout: the split kernel writes every operand's planes k-contiguous -- A as [M][Kp], B as
-// [N][Kp], Kp = K rounded up to 8 and zero padded -- transposing through an LDS tile where the
-// float64 operand is stored the other way, so the GEMM reads 16-byte vectors of 8 bf16 along
-// K for both operands and stores them to LDS unchanged; an MFMA fragment is then one 16-byte
-// LDS read.  Tiling: 512 threads (8 wave64 in a 2 x 4 grid), 128 x 128 tile of C, 64 x 32 per
-// wave as 4 x 2 MFMA blocks; K advances by 32 through double-buffered LDS holding all six
-// planes of the stage; each plane's fragments are read once and serve every product they
-// enter.  Work-groups are ordered so that the tiles sharing a B tile run on one XCD.
+// [N][Kp], Kp = K rounded up to 32 and zero padded -- transposing through an LDS tile where the
+// float64 operand is stored the other way, so the GEMM moves 16-byte vectors of 8 bf16 along
+// K for both operands and an MFMA fragment is one 16-byte LDS read.  Tiling: 512 threads
+// (8 wave64 in a 2 x 4 grid), 128 x 128 tile of C, 64 x 32 per wave as 4 x 2 MFMA blocks; K
+// advances by 32 through a three-stage LDS ring filled by direct global-to-LDS loads, so the
+// loads of the stage two steps ahead overlap the products of the current one; each plane's
+// fragments are read once and serve every product they enter.  Work-groups are ordered so
+// that the tiles sharing a B tile run on one XCD.
 #include "common.h"
 
 namespace tatrg {
@@ -26,7 +27,13 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8, NT = 512;
+constexpr int BM = 128, BN = 128, BK = 32, NT = 512;
+constexpr int NSTAGE = 3;                    // LDS ring: 3 x 48 KB
+constexpr int STAGE_UNITS = 2 * 3 * 8 * 64;  // 16-byte units per stage
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at their
+// maxima): wait until at most 6, or 0, vector-memory operations are outstanding
+constexpr unsigned WAIT_VM6 = 0x0F76u, WAIT_VM0 = 0x0F70u;
+typedef __attribute__((address_space(3))) void* lds_ptr;
 constexpr int LO_FLUSH_TILES = 4;  // float32 window of the small products: 4 x 32 values of K
 constexpr int ST = 64;             // split kernel tile (rows x K)
 
@@ -92,10 +99,15 @@ struct BArgs {
   int tiles_m, tiles_n;
 };
 
+// One 128 x 128 tile of C per work-group.  Operand tiles move from global memory straight
+// into LDS (global_load_lds_dwordx4, no staging registers) through a ring of NSTAGE stages of
+// BK = 32: the loads for stage kt + 2 are in flight while stage kt is multiplied.  A stage is
+// 48 blocks of 1 KB (2 operands x 3 planes x 8 row blocks of 16 rows x 32 k); lane l of the
+// wave that fills a block writes unit l = 4 r + (c ^ (r / 4 % 4)) with the 16-byte chunk c
+// of row r, a swizzle under which the 16 lanes of each fragment read hit distinct banks.
 __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
   const GemmArgs& g = ba.g;
-  __shared__ uint16_t As[2][3][BM][KP];
-  __shared__ uint16_t Bs[2][3][BN][KP];
+  __shared__ __attribute__((aligned(1024))) uint4 lds[NSTAGE][STAGE_UNITS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;
@@ -109,37 +121,24 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int64_t M = g.M, N = g.N, Kp = ba.Kp;
 
-  // A stage: 3 planes x 128 rows x 4 chunks of 8 bf16; B likewise: 3072 chunks, 6 per thread
-  uint4 stg[6];
-  auto load = [&](int64_t k0) {
+  // Source of this lane's unit in each of the wave's six blocks (block wave + 8 i).  Rows past
+  // M or N read the last valid row: they only feed rows and columns of C that are not stored.
+  const int ur = lane >> 2, uc = (lane & 3) ^ ((ur >> 2) & 3);
+  const uint16_t* src[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const int e = tid + i * NT;
-      const int op = e / 1536, rem = e - op * 1536;
-      const int p = rem >> 9, row = (rem & 511) >> 2, kc = rem & 3;
-      const int64_t k = k0 + kc * 8;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (op == 0) {
-        const int64_t m = m0 + row;
-        if (m < M && k < Kp)
-          v = *reinterpret_cast<const uint4*>(ba.a[p] + b * ba.sAp + m * Kp + k);
-      } else {
-        const int64_t n = n0 + row;
-        if (n < N && k < Kp)
-          v = *reinterpret_cast<const uint4*>(ba.b[p] + b * ba.sBp + n * Kp + k);
-      }
-      stg[i] = v;
-    }
-  };
-  auto store = [&](int buf) {
+  for (int i = 0; i < 6; ++i) {
+    const int bi = wave + 8 * i;
+    const int op = bi / 24, p = (bi % 24) / 8, rb = bi % 8;
+    const int64_t lim = (op == 0 ? M : N) - 1;
+    int64_t row = (op == 0 ? m0 : n0) + rb * 16 + ur;
+    if (row > lim) row = lim;
+    src[i] = (op == 0 ? ba.a[p] + b * ba.sAp : ba.b[p] + b * ba.sBp) + row * Kp + uc * 8;
+  }
+  auto issue = [&](int stage, int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const int e = tid + i * NT;
-      const int op = e / 1536, rem = e - op * 1536;
-      const int p = rem >> 9, row = (rem & 511) >> 2, kc = rem & 3;
-      uint16_t* dst = (op == 0) ? &As[buf][p][row][kc * 8] : &Bs[buf][p][row][kc * 8];
-      *reinterpret_cast<uint4*>(dst) = stg[i];
-    }
+    for (int i = 0; i < 6; ++i)
+      __builtin_amdgcn_global_load_lds((const void*)(src[i] + k0),
+                                       (lds_ptr)&lds[stage][(wave + 8 * i) * 64], 16, 0, 0);
   };
 
   f4 hi[4][2], lo[4][2];
@@ -154,25 +153,32 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
       for (int v = 0; v < 4; ++v) dacc[i][j][v] = 0.0;
     }
 
-  const int64_t nk = (Kp + BK - 1) / BK;
-  if (nk > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  const int kg = 8 * (lane >> 4), rl = lane & 15;
+  const int64_t nk = Kp / BK;
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, BK);
+  // fragment unit of this lane: row l % 16 of a block, 16-byte chunk l / 16
+  const int rl = lane & 15, fpos = rl * 4 + ((lane >> 4) ^ ((rl >> 2) & 3));
   for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    const int cur = (int)(kt % NSTAGE);
+    // Stage kt has landed once at most the six loads of stage kt + 1 are outstanding; the
+    // barrier makes every wave's blocks visible and ends all reads of stage kt - 1, whose
+    // buffer the loads of stage kt + 2 then refill.
+    if (kt + 1 < nk)
+      __builtin_amdgcn_s_waitcnt(WAIT_VM6);
+    else
+      __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+    __builtin_amdgcn_s_barrier();
+    if (kt + 2 < nk) issue((int)((kt + 2) % NSTAGE), (kt + 2) * BK);
     bf16x8 fa[3][4], fb[3][2];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        fa[p][t] = *reinterpret_cast<const bf16x8*>(&As[cur][p][wm * 64 + t * 16 + rl][kg]);
+        fa[p][t] = *reinterpret_cast<const bf16x8*>(&lds[cur][(p * 8 + wm * 4 + t) * 64 + fpos]);
 #pragma unroll
       for (int t = 0; t < 2; ++t)
-        fb[p][t] = *reinterpret_cast<const bf16x8*>(&Bs[cur][p][wn * 32 + t * 16 + rl][kg]);
+        fb[p][t] =
+            *reinterpret_cast<const bf16x8*>(&lds[cur][((3 + p) * 8 + wn * 2 + t) * 64 + fpos]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -203,8 +209,6 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
           lo[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    if (kt + 1 < nk) store(cur ^ 1);
-    __syncthreads();
   }
 
   // D fragment of v_mfma_f32_16x16x32_bf16: lane l, element v holds row 4*(l/16) + v,
@@ -232,7 +236,7 @@ int64_t plane_batches(const GemmArgs& g, bool a_side) {
   return s == 0 ? 1 : g.batch;
 }
 
-int64_t kpad(int64_t K) { return ((K + 7) / 8) * 8; }
+int64_t kpad(int64_t K) { return ((K + BK - 1) / BK) * BK; }
 
 }  // namespace
 
