@@ -28,6 +28,10 @@ class TatrgError(RuntimeError):
 def _load():
     if not os.path.exists(library_path):
         raise ImportError("libtatrg.so is not built; run python paper_2412_14104_amd/build.py")
+    # torch (which owns the device memory and streams handed to the library) is imported
+    # first, so its HIP runtime is initialised before the library's; loading the library
+    # first leaves the library's runtime without a device
+    import torch  # noqa: F401
     return ctypes.CDLL(library_path)
 
 
