@@ -6,7 +6,8 @@
 //
 // Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) computes a 128 x 128 tile of C;
 // each wave owns 64 x 64 = 4 x 4 MFMA blocks of 16 x 16 held in 64 accumulator doubles per
-// lane.  K advances in steps of BK = 8 through a double-buffered LDS stage (A as [k][m], B as
+// lane.  Products with N <= 96 (a tall panel times a small matrix) use tiles 32, 64 or 96
+// wide, so the matrix cores do no work on padding columns.  K advances in steps of BK = 8 through a double-buffered LDS stage (A as [k][m], B as
 // [k][n], so MFMA fragments are read with unit stride); the next stage's global loads are
 // issued before the MFMAs of the current one.  Global loads are mapped so that consecutive
 // lanes read consecutive addresses of whichever dimension is contiguous in memory (the
@@ -23,7 +24,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 8, PAD = 4, NT = 256;
-constexpr int EA = BM * BK / NT, EB = BN * BK / NT;  // staged elements per thread
+constexpr int EA = BM * BK / NT;  // staged A elements per thread
 
 struct KArgs {
   GemmArgs g;
@@ -35,8 +36,11 @@ struct KArgs {
 // PLAIN: C = op(A) op(B) (alpha = 1, beta = 0, or a split-K partial).  The accumulators are
 // then stored straight from the accumulation registers; the general epilogue (scaling by
 // alpha, adding beta C) moves them to vector registers first and halves the occupancy.
-template <bool TA, bool TB, bool PLAIN>
+// TN: MFMA blocks per wave along N (tile width 32 TN): narrower tiles for products with
+// N <= 96 (panel times a small matrix) so that no matrix-core work is spent on padding.
+template <bool TA, bool TB, bool PLAIN, int TN>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
+  constexpr int BNT = 32 * TN, EB = BNT * BK / NT;
   const GemmArgs& g = ka.g;
   if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
   // tile: blockIdx.(x, y) = (N tile, M tile); for a symmetric split-K product blockIdx.x
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     tile_m = t - tn * (tn + 1) / 2;
   }
   __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  __shared__ double Bs[2][BK][BNT + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   const double* A = g.A + b * g.sA + (TA ? kb * g.lda : kb);
   const double* B = g.B + b * g.sB + (TB ? kb : kb * g.ldb);
   const int64_t m0 = (int64_t)tile_m * BM;
-  const int64_t n0 = (int64_t)tile_n * BN;
+  const int64_t n0 = (int64_t)tile_n * BNT;
   const int64_t M = g.M, N = g.N;
 
   // element e of a stage: A tile row/k and B tile column/k
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     if (TA) { r = e % BM; kk = e / BM; } else { r = e / BK; kk = e % BK; }
   };
   auto b_ck = [&](int e, int& c, int& kk) {
-    if (TB) { c = e / BK; kk = e % BK; } else { c = e % BN; kk = e / BN; }
+    if (TB) { c = e / BK; kk = e % BK; } else { c = e % BNT; kk = e / BNT; }
   };
   double ra[EA], rb[EB];
   auto load = [&](int64_t k0) {
@@ -109,11 +113,11 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     }
   };
 
-  d4 acc[4][4];
+  d4 acc[4][TN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int64_t nk = (K + BK - 1) / BK;
   if (nk > 0) {
@@ -126,16 +130,17 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double a[4], bb[4];
+      double a[4], bb[TN];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < 4; ++t)
         a[t] = As[cur][kk + (lane >> 4)][wm * 64 + t * 16 + (lane & 15)];
-        bb[t] = Bs[cur][kk + (lane >> 4)][wn * 64 + t * 16 + (lane & 15)];
-      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+        bb[t] = Bs[cur][kk + (lane >> 4)][wn * TN * 16 + t * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) store(cur ^ 1);
@@ -161,11 +166,11 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
-        const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int64_t col = n0 + wn * TN * 16 + j * 16 + (lane & 15);
         if (row < M && col < N) {
           if (PLAIN) {
             C[row * ldc + col] = acc[i][j][v];
@@ -290,26 +295,39 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t l
     }
 }
 
+template <bool TA, bool TB, int TN>
+void launch_t(const KArgs& ka, hipStream_t st) {
+  const GemmArgs& g = ka.g;
+  const int64_t tn = (g.N + 32 * TN - 1) / (32 * TN), tm = (g.M + BM - 1) / BM;
+  dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(g.batch * ka.kparts));
+  if (g.sym && ka.kparts > 1) grid = dim3((unsigned)(tn * (tn + 1) / 2), 1u,
+                                          (unsigned)(g.batch * ka.kparts));
+  const bool plain = ka.kparts > 1 || (g.alpha == 1.0 && g.beta == 0.0);
+  if (plain)
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true, TN>), grid, dim3(NT), 0, st, ka);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false, TN>), grid, dim3(NT), 0, st, ka);
+}
+
 template <bool TA, bool TB>
-void launch_b(const KArgs& ka, dim3 grid, hipStream_t st) {
-  const bool plain = ka.kparts > 1 || (ka.g.alpha == 1.0 && ka.g.beta == 0.0);
-  if (plain) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true>), grid, dim3(NT), 0, st, ka);
-  else hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false>), grid, dim3(NT), 0, st, ka);
+void launch_b(const KArgs& ka, hipStream_t st) {
+  // the triangular tile order of symmetric split-K products needs square tiles
+  const int64_t N = ka.g.N;
+  if ((ka.g.sym && ka.kparts > 1) || N > 96) launch_t<TA, TB, 4>(ka, st);
+  else if (N > 64) launch_t<TA, TB, 3>(ka, st);
+  else if (N > 32) launch_t<TA, TB, 2>(ka, st);
+  else launch_t<TA, TB, 1>(ka, st);
 }
 
 void launch(const KArgs& ka, hipStream_t st) {
   const GemmArgs& g = ka.g;
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  const int64_t tn = (g.N + BN - 1) / BN, tm = (g.M + BM - 1) / BM;
-  dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(g.batch * ka.kparts));
-  if (g.sym && ka.kparts > 1) grid = dim3((unsigned)(tn * (tn + 1) / 2), 1u,
-                                          (unsigned)(g.batch * ka.kparts));
   if (g.ta) {
-    if (g.tb) launch_b<true, true>(ka, grid, st);
-    else launch_b<true, false>(ka, grid, st);
+    if (g.tb) launch_b<true, true>(ka, st);
+    else launch_b<true, false>(ka, st);
   } else {
-    if (g.tb) launch_b<false, true>(ka, grid, st);
-    else launch_b<false, false>(ka, grid, st);
+    if (g.tb) launch_b<false, true>(ka, st);
+    else launch_b<false, false>(ka, st);
   }
 }
 

@@ -44,6 +44,9 @@ GEMM_CASES = [
     (1, 1, 1, False, False), (17, 33, 5, False, False), (128, 128, 16, False, False),
     (200, 130, 70, True, False), (130, 200, 70, False, True), (257, 300, 1000, True, True),
     (64, 3, 4096, False, False), (5, 700, 33, True, False),
+    # narrow tiles (N <= 32, 64, 96) with every transpose combination
+    (1000, 96, 96, False, False), (300, 96, 70, False, True), (129, 65, 40, True, True),
+    (77, 50, 19, True, False), (260, 32, 96, True, True), (33, 90, 8, False, True),
 ]
 
 
