@@ -438,10 +438,10 @@ __global__ void add_shift_kernel(double* A, int n, double shift_rel) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) M[(int64_t)i * n + i] += d;
 }
 
-// Factor the diagonal block at (j, j) (jb <= 64, redundantly in every workgroup) and solve
-// the panel rows below it: L[i, j:j+jb] = A[i, j:j+jb] L_jj^{-T}.
-__global__ __launch_bounds__(256) void chol_panel_kernel(double* Aall, int n, int j, int jb,
-                                                         int* flag) {
+// Factor the diagonal block at (j, j) (jb <= 64) of every matrix of the batch (one work-group
+// each) and write L_jj back, zero above its diagonal.
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* Aall, int n, int j, int jb,
+                                                        int* flag) {
   __shared__ double D[64][65];
   double* A = Aall + (int64_t)blockIdx.y * n * n;
   const int tid = threadIdx.x;
@@ -467,23 +467,42 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double* Aall, int n, in
     }
     __syncthreads();
   }
-  if (blockIdx.x == 0) {
-    for (int idx = tid; idx < jb * jb; idx += 256) {
-      const int r = idx / jb, c = idx - (idx / jb) * jb;
-      A[(int64_t)(j + r) * n + j + c] = (c <= r) ? D[r][c] : 0.0;
-    }
+  for (int idx = tid; idx < jb * jb; idx += 256) {
+    const int r = idx / jb, c = idx - (idx / jb) * jb;
+    A[(int64_t)(j + r) * n + j + c] = (c <= r) ? D[r][c] : 0.0;
   }
+}
+
+// Panel rows below the diagonal block: L[i, j:j+jb] = A[i, j:j+jb] L_jj^{-T} by forward
+// substitution, one row per thread held in registers (64 rows per work-group).
+__global__ __launch_bounds__(64) void chol_trsm_kernel(double* Aall, int n, int j, int jb) {
+  __shared__ double D[64][65];
+  double* A = Aall + (int64_t)blockIdx.y * n * n;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < jb * jb; idx += 64) {
+    const int r = idx / jb, c = idx - (idx / jb) * jb;
+    D[r][c] = A[(int64_t)(j + r) * n + j + c];
+  }
+  __syncthreads();
   const int rows_below = n - j - jb;
-  const int per = (rows_below + gridDim.x - 1) / gridDim.x;
-  const int rb = blockIdx.x * per;
-  for (int rr = rb + tid; rr < rb + per && rr < rows_below; rr += 256) {
-    double* row = A + (int64_t)(j + jb + rr) * n + j;
-    for (int c = 0; c < jb; ++c) {  // forward substitution in place: row <- row L_jj^{-T}
-      double s = row[c];
-      for (int l = 0; l < c; ++l) s -= row[l] * D[c][l];
-      row[c] = s / D[c][c];
+  const int rr = blockIdx.x * 64 + tid;
+  if (rr >= rows_below) return;
+  double* row = A + (int64_t)(j + jb + rr) * n + j;
+  double x[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) x[c] = (c < jb) ? row[c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    if (c < jb) {
+      double s = x[c];
+#pragma unroll
+      for (int l = 0; l < c; ++l) s -= x[l] * D[c][l];
+      x[c] = s / D[c][c];
     }
   }
+#pragma unroll
+  for (int c = 0; c < 64; ++c)
+    if (c < jb) row[c] = x[c];
 }
 
 __global__ void zero_upper_kernel(double* A, int n, int batch) {
@@ -746,11 +765,11 @@ void cholesky_shifted(double* A, int n, int batch, double shift_rel, int* flag,
       g.batch = batch;
       gemm_f64(g, st);
     }
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1, batch), dim3(256), 0, st, A, n, j, jb, flag);
     const int rows_below = n - j - jb;
-    int chunks = (rows_below + 255) / 256;
-    if (chunks < 1) chunks = 1;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(chunks, batch), dim3(256), 0, st, A, n, j, jb,
-                       flag);
+    if (rows_below > 0)
+      hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows_below + 63) / 64, batch), dim3(64), 0, st,
+                         A, n, j, jb);
   }
   const int64_t total = (int64_t)n * n * batch;
   int64_t blocks = (total + 255) / 256;

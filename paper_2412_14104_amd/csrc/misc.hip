@@ -93,6 +93,51 @@ __global__ void permute_kernel(const double* __restrict__ in, double* __restrict
   }
 }
 
+// A permutation whose output-innermost leg is not the input-innermost leg, as 32 x 32 tiles
+// of those two legs staged through LDS: reads run along the input-innermost leg and writes
+// along the output-innermost leg, so both are contiguous.  Work-group w takes tiles w, w + G,
+// ...; tile index = (tile along la) + ta (tile along lb + tb (the other output legs, last
+// fastest)).
+struct TileArgs {
+  int rank;
+  int la, lb;  // output positions: la = rank - 1, lb = the leg that is innermost in the input
+  int64_t out_dims[6], in_stride_for_out[6], out_stride[6];
+  int64_t ta, tb;  // tiles along la and lb
+};
+
+__global__ __launch_bounds__(256) void permute_tiled_kernel(const double* __restrict__ in,
+                                                            double* __restrict__ out,
+                                                            TileArgs t, int64_t ntiles) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t sa_in = t.in_stride_for_out[t.la], sb_out = t.out_stride[t.lb];
+  for (int64_t w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    int64_t rem = w;
+    const int64_t ia = rem % t.ta;
+    rem /= t.ta;
+    const int64_t ib = rem % t.tb;
+    rem /= t.tb;
+    int64_t in_base = 0, out_base = 0;
+    for (int k = t.rank - 1; k >= 0; --k) {
+      if (k == t.la || k == t.lb) continue;
+      const int64_t d = t.out_dims[k];
+      const int64_t q = rem / d, i = rem - q * d;
+      in_base += i * t.in_stride_for_out[k];
+      out_base += i * t.out_stride[k];
+      rem = q;
+    }
+    const int64_t a0 = ia * 32, b0 = ib * 32;
+    const int na = (int)(t.out_dims[t.la] - a0 < 32 ? t.out_dims[t.la] - a0 : 32);
+    const int nb = (int)(t.out_dims[t.lb] - b0 < 32 ? t.out_dims[t.lb] - b0 : 32);
+    __syncthreads();  // the previous tile has been written out
+    if (tx < nb)
+      for (int a = ty; a < na; a += 8) tile[a][tx] = in[in_base + (a0 + a) * sa_in + b0 + tx];
+    __syncthreads();
+    if (tx < na)
+      for (int b = ty; b < nb; b += 8) out[out_base + (b0 + b) * sb_out + a0 + tx] = tile[tx][b];
+  }
+}
+
 __global__ void scale_cols_kernel(double* x, const double* s, int64_t rows, int64_t cols,
                                   int64_t ld) {
   const int64_t total = rows * cols;
@@ -256,9 +301,32 @@ void permute(const double* in, double* out, int rank, const int64_t* dims, const
     in_stride[k] = s;
     s *= dims[k];
   }
+  int lb = rank - 1;
   for (int k = 0; k < rank; ++k) {
     pa.out_dims[k] = dims[perm[k]];
     pa.in_stride_for_out[k] = in_stride[perm[k]];
+    if (perm[k] == rank - 1) lb = k;
+  }
+  const int la = rank - 1;
+  if (lb != la && pa.out_dims[la] >= 8 && pa.out_dims[lb] >= 8) {
+    TileArgs t;
+    t.rank = rank;
+    t.la = la;
+    t.lb = lb;
+    int64_t os = 1;
+    for (int k = rank - 1; k >= 0; --k) {
+      t.out_dims[k] = pa.out_dims[k];
+      t.in_stride_for_out[k] = pa.in_stride_for_out[k];
+      t.out_stride[k] = os;
+      os *= pa.out_dims[k];
+    }
+    t.ta = (pa.out_dims[la] + 31) / 32;
+    t.tb = (pa.out_dims[lb] + 31) / 32;
+    const int64_t ntiles = s / (pa.out_dims[la] * pa.out_dims[lb]) * t.ta * t.tb;
+    const int64_t g = ntiles < 1048576 ? ntiles : 1048576;
+    hipLaunchKernelGGL(permute_tiled_kernel, dim3((unsigned)g), dim3(256), 0, st, in, out, t,
+                       ntiles);
+    return;
   }
   hipLaunchKernelGGL(permute_kernel, dim3(grid_for(s)), dim3(TPB), 0, st, in, out, pa, s);
 }
