@@ -1,12 +1,15 @@
-"""Self-sensitivity of the oracle's singular spectra, per RG step (test infrastructure).
+"""Self-sensitivity of the oracle's per-step records (test infrastructure).
 
-Runs the FP64 oracle (oracle/ only) for a preset with relative noise of 1e-15 added to
-(Phi, Psi) after every step, and records per step the largest deviation of each stored
-spectrum from the unperturbed run in tests/golden/<name>.json, relative to that spectrum's
-maximum.  The parity tests bound the GPU's spectra by a multiple of this: the RG flow
+Runs the FP64 oracle (oracle/ only) with relative noise of 1e-15 added to (Phi, Psi) after
+every step and records, per step, how far the perturbed run moves from the unperturbed one
+stored in tests/golden/.  The parity tests bound the GPU by a multiple of this: the RG flow
 amplifies rounding, and this measures how much for the oracle itself.  Usage:
-    python tests/golden/make_sensitivity.py C3      # about 70 minutes on 8 cores
-writes tests/golden/<name>_spectra_sensitivity.json.
+    python tests/golden/make_sensitivity.py C3          # about 70 minutes on 8 cores
+        spectra (relative to each spectrum's maximum) of the run in C3.json
+        -> tests/golden/C3_spectra_sensitivity.json
+    python tests/golden/make_sensitivity.py C4_subset   # about 50 minutes on 2 cores
+        order parameter X^(m) of the three runs in C4_subset.json
+        -> tests/golden/C4_subset_X_sensitivity.json
 """
 import json
 import os
@@ -51,5 +54,31 @@ def main(name):
                              "step, written by tests/golden/make_sensitivity.py"}, fh, indent=1)
 
 
+def main_x(name):
+    g = json.load(open(os.path.join(HERE, name + ".json")))
+    chi, r, q, seed, n = g["chi"], g["r"], g["q"], g["seed"], g["n_steps"]
+    out = []
+    for run in g["runs"]:
+        rng = np.random.default_rng(NOISE_SEED)
+        phi, psi = tatrg.initial_state(run["beta"], chi)
+        dev = []
+        for k in range(n):
+            phi, psi, info = tatrg.step(phi, psi, k, chi, r, q, seed)
+            dev.append(abs(info["X"] - run["X"][k]))
+            phi = phi + NOISE * np.abs(phi).max() * rng.standard_normal(phi.shape)
+            psi = psi + NOISE * np.abs(psi).max() * rng.standard_normal(psi.shape)
+        dev.append(abs(tatrg.order_parameter(phi, psi, n) - run["X"][n]))
+        print(run["beta"], " ".join("%.1e" % d for d in dev), flush=True)
+        out.append({"beta": run["beta"], "X_dev": dev})
+    with open(os.path.join(HERE, name + "_X_sensitivity.json"), "w") as fh:
+        json.dump({"config": name, "noise": NOISE, "noise_seed": NOISE_SEED, "runs": out,
+                   "source": "oracle/tatrg.py step() with 1e-15 relative noise after every "
+                             "step, written by tests/golden/make_sensitivity.py"}, fh, indent=1)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "C3")
+    which = sys.argv[1] if len(sys.argv) > 1 else "C3"
+    if which.endswith("_subset"):
+        main_x(which)
+    else:
+        main(which)

@@ -115,12 +115,21 @@ def test_batch_lognorm_and_bad_temperatures(pkg):
 
 def test_scan_subset_matches_oracle(pkg):
     """Three temperatures of the chi = 24 scan (first, middle, last of 64 in [0.140, 0.160]),
-    40 steps, as one batch, against the oracle's stored runs."""
+    40 steps, as one batch, against the oracle's stored runs.
+
+    f to REL_F.  X^(m) per step to max(X_TOL, 10 x the oracle's own drift at that step when
+    perturbed by 1e-15 relative noise after every step) -- tests/golden/
+    C4_subset_X_sensitivity.json, written by tests/golden/make_sensitivity.py from the oracle
+    alone.  Over 40 steps at chi = 24 the RG flow amplifies rounding in the subleading part of
+    the spectrum, and near the fixed points X - 1 or 2 - X is set by exactly that part."""
     path = os.path.join(HERE, "golden", "C4_subset.json")
-    if not os.path.exists(path):
-        pytest.skip("golden C4_subset not generated")
+    spath = os.path.join(HERE, "golden", "C4_subset_X_sensitivity.json")
+    if not os.path.exists(path) or not os.path.exists(spath):
+        pytest.skip("golden C4_subset or its X sensitivity not generated")
     with open(path) as fh:
         g = json.load(fh)
+    with open(spath) as fh:
+        sens = json.load(fh)["runs"]
     betas = [run["beta"] for run in g["runs"]]
     print("case C4 subset", betas, flush=True)
     eng = pkg.Engine(g["chi"], g["r"], g["q"], g["n_steps"], seed=g["seed"],
@@ -132,7 +141,11 @@ def test_scan_subset_matches_oracle(pkg):
     for b, run in enumerate(g["runs"]):
         assert abs(fs[b] - run["f"]) <= REL_F * abs(run["f"]), (b, fs[b], run["f"])
         assert abs(ls[b] - run["lnZV"]) <= REL_F * abs(run["lnZV"])
+        assert sens[b]["beta"] == run["beta"]
         xg = gpu_x(eng, g["n_steps"], b)
-        worst = max(abs(a - c) for a, c in zip(xg, run["X"]))
-        print("beta", run["beta"], "worst |dX|", worst, flush=True)
-        assert worst <= X_TOL, (b, worst)
+        worst = 0.0
+        for m, (a, c) in enumerate(zip(xg, run["X"])):
+            bound = max(X_TOL, 10.0 * sens[b]["X_dev"][m])
+            worst = max(worst, abs(a - c) / bound)
+            assert abs(a - c) <= bound, (b, m, a, c, bound)
+        print("beta", run["beta"], "worst |dX| / bound", worst, flush=True)
