@@ -260,23 +260,42 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t l
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int64_t r = r0; r < r1; r += 4) {
-    const int64_t row = r + kr;
-    const bool ok = row < r1;
-    double xa[NB], yb[NB];
+  // Rows go in batches of PF steps of four; the loads of the next batch are issued before the
+  // products of the current one, so a wave keeps 6 PF (or 12 PF) loads in flight.  Rows are
+  // accumulated in increasing order, one step at a time, as without the batching.
+  constexpr int PF = SYM ? 4 : (NB >= 5 ? 1 : (NB == 4 ? 2 : 4));
+  constexpr int PY = SYM ? 1 : PF;
+  auto load = [&](double (&x)[PF][NB], double (&y)[PY][NB], int64_t rb) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int col = b * 16 + cl;
-      xa[b] = (ok && col < M) ? X[row * ldx + col] : 0.0;
-      yb[b] = SYM ? xa[b] : ((ok && col < N) ? Y[row * ldy + col] : 0.0);
+    for (int p = 0; p < PF; ++p) {
+      const int64_t row = rb + 4 * p + kr;
+      const bool ok = row < r1;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int col = b * 16 + cl;
+        x[p][b] = (ok && col < M) ? X[row * ldx + col] : 0.0;
+        if (!SYM) y[SYM ? 0 : p][b] = (ok && col < N) ? Y[row * ldy + col] : 0.0;
+      }
     }
+  };
+  auto compute = [&](double (&x)[PF][NB], double (&y)[PY][NB]) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+    for (int p = 0; p < PF; ++p)
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (!SYM || i <= j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (!SYM || i <= j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                x[p][i], SYM ? x[p][j] : y[SYM ? 0 : p][j], acc[i][j], 0, 0, 0);
+  };
+  double xa[PF][NB], ya[PY][NB], xb[PF][NB], yb[PY][NB];
+  load(xa, ya, r0);
+  for (int64_t r = r0; r < r1; r += 8 * PF) {
+    load(xb, yb, r + 4 * PF);
+    compute(xa, ya);
+    load(xa, ya, r + 8 * PF);
+    compute(xb, yb);
   }
   double* out = partial + wid * (int64_t)M * N;
 #pragma unroll
