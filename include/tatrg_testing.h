@@ -22,9 +22,11 @@ extern "C" {
 /* C[b] = alpha op(A[b]) op(B[b]) + beta C[b]; op(A) M x K (A stored K x M when ta),
  * op(B) K x N (B stored N x K when tb); batch strides sA, sB, sC in elements.
  * parts > 1 splits K and sums the parts in order through `partial`
- * (parts * batch * M * N doubles).  parts < 0 selects the skinny-product kernel for
- * ta = 1, tb = 0, batch 1, M, N <= 96 (one wave per chunk of rows), with `partial` holding
- * -parts * 1024 doubles; returns -1 when the shape does not qualify.  With A == B (same
+ * (parts * batch * M * N doubles).  parts < 0 selects the skinny-product kernels for batch 1,
+ * M, N <= 96: ta = 1, tb = 0 (X^T Y over long columns, one wave per chunk of rows) or
+ * ta = 0, tb = 1 (X Y^T over long rows, one wave per chunk of columns; the general 96 x 96
+ * case is declined), with `partial` holding -parts * 1024 doubles; returns -1 when the shape
+ * does not qualify.  With A == B (same
  * pointer, stride and leading dimension), M == N and ta != tb the product is symmetric and
  * split-K computes only the tiles on and above the diagonal, mirroring the rest. */
 int tatrg_test_gemm(const double* A, const double* B, double* C, int64_t M, int64_t N,

@@ -38,7 +38,8 @@ size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
 
 // C = alpha X^T Y + beta C for the skinny shapes X (K x M), Y (K x N) with M, N <= 96
 // (GemmArgs with ta && !tb, batch 1): one wave per chunk of rows writes an M x N partial
-// sum to `partial`, summed in a fixed order afterwards.  Returns false (nothing launched)
+// sum to `partial`, summed in a fixed order afterwards.  Also C = X Y^T over long rows
+// (!ta && tb, batch 1; the general 96 x 96 case is declined), one wave per chunk of columns.  Returns false (nothing launched)
 // when the shape does not qualify or `partial` is too small.
 bool gram_tn(const GemmArgs& g, double* partial, size_t partial_doubles, hipStream_t st);
 

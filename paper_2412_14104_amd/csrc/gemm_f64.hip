@@ -314,6 +314,69 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(const double* X, int64_t l
     }
 }
 
+// Skinny products C = X Y^T with X (M x k), Y (N x k) row-major, M, N <= 16 NB, k long (the
+// rows are long).  Every wave sums its own chunk of k into partial[wave] (M x N).  Per step of
+// 16 along k, lane l reads four consecutive values k0 + 4 (l/16) + 0..3 of row 16 b + l%16, so
+// the 64 lanes of a block read 16 contiguous 128-byte row segments; MFMA j of the step then
+// pairs the j-th of those four values of X and of Y (each lane supplies the same k to both
+// operands, which is all the product needs).  SYM (X = Y, M = N): upper blocks only, mirrored.
+template <int NB, bool SYM>
+__global__ __launch_bounds__(256) void gram_nt_kernel(const double* X, int64_t ldx,
+                                                      const double* Y, int64_t ldy, int64_t k,
+                                                      int M, int N, int64_t cols_per_wave,
+                                                      int64_t nwaves, double* partial,
+                                                      const int* cond, int cond_when) {
+  if (cond && ((*cond != 0) != (cond_when != 0))) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= nwaves) return;
+  const int64_t c0 = wid * cols_per_wave;
+  const int64_t c1 = (c0 + cols_per_wave < k) ? c0 + cols_per_wave : k;
+  const int kq = 4 * (lane >> 4), rl = lane & 15;
+  d4 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = c0; c < c1; c += 16) {
+    double xa[NB][4], yb[SYM ? 1 : NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int row = b * 16 + rl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = c + kq + q;
+        xa[b][q] = (row < M && col < c1) ? X[row * ldx + col] : 0.0;
+        if (!SYM) yb[SYM ? 0 : b][q] = (row < N && col < c1) ? Y[row * ldy + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (!SYM || i <= j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                xa[i][q], SYM ? xa[j][q] : yb[SYM ? 0 : j][q], acc[i][j], 0, 0, 0);
+  }
+  double* out = partial + wid * (int64_t)M * N;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (SYM && i > j) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + (lane >> 4) + 4 * v, col = j * 16 + rl;
+        if (row < M && col < N) {
+          out[row * N + col] = acc[i][j][v];
+          if (SYM && i < j) out[col * N + row] = acc[i][j][v];
+        }
+      }
+    }
+}
+
 template <bool TA, bool TB, int TN>
 void launch_t(const KArgs& ka, hipStream_t st) {
   const GemmArgs& g = ka.g;
@@ -357,9 +420,56 @@ void gemm_f64(const GemmArgs& g, hipStream_t st) {
   launch(ka, st);
 }
 
+namespace {
+
+// C = alpha X Y^T + beta C for long rows (M, N <= 96): gram_nt_kernel, then the parts.
+bool gram_nt(const GemmArgs& g, double* partial, size_t partial_doubles, hipStream_t st) {
+  const int64_t mn = g.M * g.N;
+  int64_t nw = std::min<int64_t>(2048, (g.K + 255) / 256);   // >= 256 of k per wave
+  nw = std::min<int64_t>(nw, (int64_t)(partial_doubles / (size_t)mn));
+  if (nw < 1) return false;
+  int64_t cpw = (g.K + nw - 1) / nw;
+  cpw = ((cpw + 15) / 16) * 16;
+  nw = (g.K + cpw - 1) / cpw;
+  const int nbk = (int)((std::max(g.M, g.N) + 15) / 16);
+  const dim3 grid((unsigned)((nw + 3) / 4));
+  const int cw = g.cond_when ? 1 : 0;
+  const bool sym = g.A == g.B && g.lda == g.ldb && g.M == g.N;
+  switch (nbk) {
+#define GRAM_NT_CASE(NB)                                                                      \
+  case NB:                                                                                    \
+    if (sym)                                                                                  \
+      hipLaunchKernelGGL((gram_nt_kernel<NB, true>), grid, dim3(256), 0, st, g.A, g.lda, g.B, \
+                         g.ldb, g.K, (int)g.M, (int)g.N, cpw, nw, partial, g.cond, cw);       \
+    else                                                                                      \
+      hipLaunchKernelGGL((gram_nt_kernel<NB, false>), grid, dim3(256), 0, st, g.A, g.lda,     \
+                         g.B, g.ldb, g.K, (int)g.M, (int)g.N, cpw, nw, partial, g.cond, cw);  \
+    break;
+    GRAM_NT_CASE(1)
+    GRAM_NT_CASE(2)
+    GRAM_NT_CASE(3)
+    GRAM_NT_CASE(4)
+    GRAM_NT_CASE(5)
+#undef GRAM_NT_CASE
+    case 6:  // the general 96 x 96 product does not fit the registers: GEMM path
+      if (!sym) return false;
+      hipLaunchKernelGGL((gram_nt_kernel<6, true>), grid, dim3(256), 0, st, g.A, g.lda, g.B,
+                         g.ldb, g.K, (int)g.M, (int)g.N, cpw, nw, partial, g.cond, cw);
+      break;
+    default:
+      return false;
+  }
+  hipLaunchKernelGGL(parts_reduce_kernel, dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0, st,
+                     partial, g.C, g.M, g.N, g.ldc, nw, g.alpha, g.beta, g.cond, cw);
+  return true;
+}
+
+}  // namespace
+
 bool gram_tn(const GemmArgs& g, double* partial, size_t partial_doubles, hipStream_t st) {
-  if (!(g.ta && !g.tb) || g.batch != 1 || g.M > 96 || g.N > 96 || g.M < 1 || g.N < 1)
-    return false;
+  if (g.batch != 1 || g.M > 96 || g.N > 96 || g.M < 1 || g.N < 1) return false;
+  if (!g.ta && g.tb) return gram_nt(g, partial, partial_doubles, st);
+  if (!(g.ta && !g.tb)) return false;
   const int64_t mn = g.M * g.N;
   int64_t nw = std::min<int64_t>(2048, (g.K + 63) / 64);   // >= 64 rows per wave
   nw = std::min<int64_t>(nw, (int64_t)(partial_doubles / (size_t)mn));

@@ -164,6 +164,38 @@ def test_skinny_gram_kernel(lib, m, n, k, same):
     assert np.all(np.abs(got - ref) <= bound), np.abs(got - ref).max()
 
 
+@pytest.mark.parametrize("m,n,k,same", [(32, 32, 1048576, True), (96, 96, 300001, True),
+                                        (40, 17, 100003, False), (70, 70, 9000, True),
+                                        (33, 65, 4099, False), (1, 1, 4096, False)])
+def test_skinny_row_gram_kernel(lib, m, n, k, same):
+    """C = alpha X Y^T + beta C with X (m x k), Y (n x k) row-major and long rows: the kernel
+    behind the Grams over rows (same=True: one buffer as X and Y, upper blocks mirrored)."""
+    rng = np.random.default_rng(m + 3 * n + k)
+    x = rng.standard_normal((m, k))
+    y = x if same else rng.standard_normal((n, k))
+    c0 = rng.standard_normal((m, n))
+    dx, dc = dev(x), dev(c0)
+    dy = dx if same else dev(y)
+    part = torch.empty(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    rc = lib.tatrg_test_gemm(vp(dx), vp(dy), vp(dc), m, n, k, k, k, n, 0, 1, 0.5, 2.0, 1, 0, 0,
+                             0, -(part.numel() // 1024), vp(part), stream())
+    assert rc == 0
+    ref = 0.5 * x @ y.T + 2.0 * c0
+    bound = 0.5 * gemm_bound(x, y.T, k) + 2.0 * np.abs(c0) * 1e-16
+    got = host(dc)
+    assert np.all(np.abs(got - ref) <= bound), np.abs(got - ref).max()
+
+
+def test_skinny_row_gram_declines_the_general_96_case(lib):
+    """The general (non-symmetric) 96 x 96 row product is left to the tiled GEMM."""
+    x = dev(np.ones((96, 5000)))
+    y = dev(np.ones((96, 5000)))
+    c = torch.zeros((96, 96), dtype=torch.float64, device="cuda")
+    part = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_gemm(vp(x), vp(y), vp(c), 96, 96, 5000, 5000, 5000, 96, 0, 1, 1.0,
+                               0.0, 1, 0, 0, 0, -1024, vp(part), stream()) == -1
+
+
 TSQR_CASES = [(10, 1), (100, 7), (1000, 32), (5000, 96), (300000, 32), (120000, 96), (96, 96)]
 
 
