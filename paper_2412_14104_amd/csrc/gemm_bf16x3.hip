@@ -74,19 +74,26 @@ __global__ __launch_bounds__(256) void split3_kernel(const double* __restrict__ 
     tile[rr][kk] = (r < R && k < K) ? (trans ? xb[k * ld + r] : xb[r * ld + k]) : 0.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < ST * ST; idx += 256) {
-    const int rr = idx / ST, kk = idx % ST;
+  // four consecutive k per thread: one 8-byte store per plane (Kp is a multiple of 4 and the
+  // tile starts at a multiple of 64, so a group of four is either wholly inside or outside)
+  for (int idx = tid; idx < ST * ST / 4; idx += 256) {
+    const int rr = idx / (ST / 4), kk = 4 * (idx % (ST / 4));
     const int64_t r = r0 + rr, k = k0 + kk;
     if (r < R && k < Kp) {
-      const double v = tile[rr][kk];
-      const uint16_t a = bf16_rne((float)v);
-      const double r1 = v - bf16_to_double(a);
-      const uint16_t c = bf16_rne((float)r1);
-      const double r2 = r1 - bf16_to_double(c);
+      uint16_t a[4], c[4], e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = tile[rr][kk + q];
+        a[q] = bf16_rne((float)v);
+        const double r1 = v - bf16_to_double(a[q]);
+        c[q] = bf16_rne((float)r1);
+        const double r2 = r1 - bf16_to_double(c[q]);
+        e[q] = bf16_rne((float)r2);
+      }
       const int64_t o = (b * R + r) * Kp + k;
-      p0[o] = a;
-      p1[o] = c;
-      p2[o] = bf16_rne((float)r2);
+      *reinterpret_cast<ushort4*>(p0 + o) = make_ushort4(a[0], a[1], a[2], a[3]);
+      *reinterpret_cast<ushort4*>(p1 + o) = make_ushort4(c[0], c[1], c[2], c[3]);
+      *reinterpret_cast<ushort4*>(p2 + o) = make_ushort4(e[0], e[1], e[2], e[3]);
     }
   }
 }
