@@ -101,6 +101,27 @@ def test_gemm_bf16x3_is_fp32_class(lib, m, n, k, ta, tb):
     assert worst < 3e-7, worst
 
 
+def test_gemm_degenerate_shapes(lib):
+    """K = 0 leaves beta C; M = 0 or N = 0 touches nothing (both FP64 and split-bf16)."""
+    rng = np.random.default_rng(11)
+    c0 = rng.standard_normal((5, 7))
+    a = dev(np.ones((5, 1)))
+    b = dev(np.ones((1, 7)))
+    dc = dev(c0)
+    assert lib.tatrg_test_gemm(vp(a), vp(b), vp(dc), 5, 7, 0, 1, 7, 7, 0, 0, 1.0, 0.5, 1, 0, 0,
+                               0, 1, None, stream()) == 0
+    assert np.array_equal(host(dc), 0.5 * c0)
+    dc = dev(c0)
+    for m, n in ((0, 7), (5, 0)):
+        assert lib.tatrg_test_gemm(vp(a), vp(b), vp(dc), m, n, 1, 1, 7, 7, 0, 0, 1.0, 0.5, 1,
+                                   0, 0, 0, 1, None, stream()) == 0
+        nws = lib.tatrg_test_gemm_bf16x3_ws(m, n, 1, 1, 7, 0, 0, 1, 0, 0)
+        ws = torch.empty(max(nws, 1), dtype=torch.float64, device="cuda")
+        assert lib.tatrg_test_gemm_bf16x3(vp(a), vp(b), vp(dc), m, n, 1, 1, 7, 7, 0, 0, 1.0,
+                                          0.5, 1, 0, 0, 0, vp(ws), stream()) == 0
+    assert np.array_equal(host(dc), c0)
+
+
 def test_gemm_split_k_is_deterministic_and_correct(lib):
     rng = np.random.default_rng(5)
     m, n, k, parts = 40, 24, 50000, 16
