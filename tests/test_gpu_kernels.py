@@ -355,12 +355,14 @@ def test_philox_sketch_matches_oracle(lib):
 
 def test_permute_is_exact(lib):
     rng = np.random.default_rng(3)
-    # the last four take the tiled path (output- and input-innermost legs differ, both >= 8),
-    # with ragged tiles
+    # cases four to seven take the tiled path (output- and input-innermost legs differ, both
+    # >= 8), with ragged tiles
     for dims, perm in [((3, 4, 5), (2, 0, 1)), ((2, 3, 4, 5, 6), (1, 2, 4, 0, 3)),
                        ((5, 1, 7, 2, 3, 2), (5, 4, 3, 2, 1, 0)), ((40, 33, 50), (2, 0, 1)),
                        ((9, 37, 3, 35), (3, 0, 2, 1)), ((6, 8, 7, 9, 10), (1, 4, 0, 2, 3)),
-                       ((2, 64, 3, 32, 5, 40), (0, 5, 2, 4, 3, 1))]:
+                       ((2, 64, 3, 32, 5, 40), (0, 5, 2, 4, 3, 1)),
+                       # innermost leg kept, its length a multiple of 4 (vectorised path)
+                       ((6, 5, 7, 8), (2, 0, 1, 3)), ((3, 4, 2, 5, 12), (3, 2, 0, 1, 4))]:
         x = rng.standard_normal(dims)
         dx = dev(x)
         out = torch.empty(x.size, dtype=torch.float64, device="cuda")
