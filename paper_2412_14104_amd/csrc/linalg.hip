@@ -438,38 +438,40 @@ __global__ void add_shift_kernel(double* A, int n, double shift_rel) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) M[(int64_t)i * n + i] += d;
 }
 
-// Factor the diagonal block at (j, j) (jb <= 64) of every matrix of the batch (one work-group
-// each) and write L_jj back, zero above its diagonal.
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* Aall, int n, int j, int jb,
-                                                        int* flag) {
-  __shared__ double D[64][65];
+// Factor the diagonal block at (j, j) (jb <= 64) of every matrix of the batch (one wave each)
+// and write L_jj back, zero above its diagonal.  Lane r holds row r of the block in registers;
+// for column k the pivot comes from lane k, every lane below it scales its entry and publishes
+// it through LDS, and each lane updates its own row (right-looking, the same operations in the
+// same order as the textbook column algorithm).
+__global__ __launch_bounds__(64) void chol_diag_kernel(double* Aall, int n, int j, int jb,
+                                                       int* flag) {
+  __shared__ double lk[64];
   double* A = Aall + (int64_t)blockIdx.y * n * n;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < jb * jb; idx += 256) {
-    const int r = idx / jb, c = idx - (idx / jb) * jb;
-    D[r][c] = A[(int64_t)(j + r) * n + j + c];
-  }
-  __syncthreads();
-  __shared__ double dk;
-  for (int k = 0; k < jb; ++k) {
-    if (tid == 0) {
-      const double piv = D[k][k];
-      if (!(piv > 0.0)) flag[0] = 1;
-      dk = (piv > 0.0) ? sqrt(piv) : __builtin_nan("");
-      D[k][k] = dk;
+  const int r = threadIdx.x;
+  double row[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c)
+    row[c] = (r < jb && c < jb) ? A[(int64_t)(j + r) * n + j + c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < jb) {
+      const double piv = __shfl(row[k], k, 64);
+      if (r == 0 && !(piv > 0.0)) flag[0] = 1;
+      const double dk = (piv > 0.0) ? sqrt(piv) : __builtin_nan("");
+      if (r == k) row[k] = dk;
+      if (r > k) row[k] /= dk;
+      lk[r] = row[k];
+      __syncthreads();
+#pragma unroll
+      for (int c = k + 1; c < 64; ++c)
+        if (c <= r && r < jb) row[c] -= row[k] * lk[c];
+      __syncthreads();
     }
-    __syncthreads();
-    for (int r = k + 1 + tid; r < jb; r += 256) D[r][k] /= dk;
-    __syncthreads();
-    for (int idx = tid; idx < jb * jb; idx += 256) {
-      const int r = idx / jb, c = idx - (idx / jb) * jb;
-      if (r > k && c > k && c <= r) D[r][c] -= D[r][k] * D[c][k];
-    }
-    __syncthreads();
   }
-  for (int idx = tid; idx < jb * jb; idx += 256) {
-    const int r = idx / jb, c = idx - (idx / jb) * jb;
-    A[(int64_t)(j + r) * n + j + c] = (c <= r) ? D[r][c] : 0.0;
+  if (r < jb) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c)
+      if (c < jb) A[(int64_t)(j + r) * n + j + c] = (c <= r) ? row[c] : 0.0;
   }
 }
 
@@ -765,7 +767,7 @@ void cholesky_shifted(double* A, int n, int batch, double shift_rel, int* flag,
       g.batch = batch;
       gemm_f64(g, st);
     }
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1, batch), dim3(256), 0, st, A, n, j, jb, flag);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1, batch), dim3(64), 0, st, A, n, j, jb, flag);
     const int rows_below = n - j - jb;
     if (rows_below > 0)
       hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows_below + 63) / 64, batch), dim3(64), 0, st,
