@@ -176,3 +176,28 @@ def test_split_bf16_free_energy_matches_oracle(pkg, name):
     rel = abs(f - run["f"]) / abs(run["f"])
     print("split-bf16 |df|/|f| =", rel, flush=True)
     assert rel <= REL_F_BF16, rel
+
+
+def test_checkpoint_and_resume_is_exact(pkg):
+    """get_state after k steps, set_state into a fresh handle, and the remaining steps give the
+    uninterrupted run's free energy bit for bit (the state is Phi, Psi, k and the log-norm
+    accumulator; every sketch is a function of (seed, step, site))."""
+    chi, r, q, n, k, beta = 6, 2, 2, 16, 7, 0.15
+    print("case checkpoint chi", chi, "resume at", k, flush=True)
+    full = pkg.Engine(chi, r, q, n, seed=0)
+    f_full, l_full = full.run(beta)
+    a = pkg.Engine(chi, r, q, n, seed=0)
+    a.init(beta)
+    for _ in range(k):
+        a.step()
+    phi = torch.empty(chi ** 5, dtype=torch.float64, device="cuda")
+    psi = torch.empty(chi ** 5, dtype=torch.float64, device="cuda")
+    step, acc = a.get_state(phi, psi)
+    assert step == k
+    b = pkg.Engine(chi, r, q, n, seed=0)
+    b.init(beta)
+    b.set_state(phi, psi, step, acc)
+    for _ in range(n - k):
+        b.step()
+    f_b, l_b = b.free_energy()
+    assert f_b == f_full and l_b == l_full, (f_b, f_full)
