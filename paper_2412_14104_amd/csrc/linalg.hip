@@ -352,12 +352,21 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
         const int q = (k == 0) ? (ne - 1) : (r - k + (ne - 1)) % (ne - 1);
         double* wp = W + (size_t)p * n;
         double* wq = W + (size_t)q * n;
+        // this lane's entries of the two columns (n <= 96: at most six each), kept in
+        // registers for the rotation; the padding zeros leave the sums unchanged
+        double xr[6], yr[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          const int i = sub + 16 * t;
+          xr[t] = (i < n) ? wp[i] : 0.0;
+          yr[t] = (i < n) ? wq[i] : 0.0;
+        }
         double a = 0.0, bb = 0.0, g = 0.0;
-        for (int i = sub; i < n; i += 16) {
-          const double x = wp[i], y = wq[i];
-          a += x * x;
-          bb += y * y;
-          g += x * y;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          a += xr[t] * xr[t];
+          bb += yr[t] * yr[t];
+          g += xr[t] * yr[t];
         }
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) {
@@ -369,10 +378,13 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
           const double zeta = (bb - a) / (2.0 * g);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int i = sub; i < n; i += 16) {
-            const double x = wp[i], y = wq[i];
-            wp[i] = c * x - s * y;
-            wq[i] = s * x + c * y;
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            const int i = sub + 16 * t;
+            if (i < n) {
+              wp[i] = c * xr[t] - s * yr[t];
+              wq[i] = s * xr[t] + c * yr[t];
+            }
           }
           double* vp = V + (size_t)p * ne;
           double* vq = V + (size_t)q * ne;
