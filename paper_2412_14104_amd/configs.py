@@ -2,23 +2,15 @@
 
 Each preset is the input of one run: inverse temperature(s), bond dimension chi,
 internal-line oversampling r, QR iterations q of every randomized SVD, Philox seed and the
-number of RG steps N (a periodic lattice of 2^N sites).
+number of RG steps N (a periodic lattice of 2^N sites).  The values live in presets.json
+beside this file, which the oracle-only writers of stored results read directly.
 """
-BETA_NEAR_CRITICAL = 0.1496947
+import json
+import os
 
-PRESETS = {
-    # small case: chi = 6, 16 steps (2^16 sites), plain FP64
-    "C1": dict(betas=[0.15], chi=6, r=2, q=2, seed=0, n_steps=16, precision="fp64"),
-    # near-critical chi = 16, 40 steps (2^40 sites), FP64
-    "C2": dict(betas=[BETA_NEAR_CRITICAL], chi=16, r=2, q=2, seed=0, n_steps=40,
-               precision="fp64"),
-    # chi = 32, r = 3, 40 steps: the headline throughput workload (FP64 and split bf16)
-    "C3": dict(betas=[BETA_NEAR_CRITICAL], chi=32, r=3, q=2, seed=0, n_steps=40,
-               precision="bf16x3"),
-    # temperature scan: 64 betas in [0.140, 0.160], chi = 24
-    "C4": dict(betas=[0.140 + 0.020 * i / 63 for i in range(64)], chi=24, r=2, q=2, seed=0,
-               n_steps=40, precision="fp64"),
-    # differentiated run: chi = 48, 30 steps, three temperatures
-    "C5": dict(betas=[0.145, BETA_NEAR_CRITICAL, 0.155], chi=48, r=2, q=2, seed=0,
-               n_steps=30, precision="fp64"),
-}
+PRESETS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "presets.json")
+
+with open(PRESETS_PATH) as _fh:
+    PRESETS = {k: v for k, v in json.load(_fh).items() if not k.startswith("_")}
+
+BETA_NEAR_CRITICAL = PRESETS["C2"]["betas"][0]

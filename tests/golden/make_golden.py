@@ -16,7 +16,9 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import tatrg  # noqa: E402
-from paper_2412_14104_amd.configs import PRESETS  # noqa: E402
+# the workload presets are plain data; read them without importing the product package
+with open(os.path.join(ROOT, "paper_2412_14104_amd", "presets.json")) as _fh:
+    PRESETS = {k: v for k, v in json.load(_fh).items() if not k.startswith("_")}
 
 
 def main(names):

@@ -10,6 +10,9 @@ amplifies rounding, and this measures how much for the oracle itself.  Usage:
     python tests/golden/make_sensitivity.py C4_subset   # about 50 minutes on 2 cores
         order parameter X^(m) of the three runs in C4_subset.json
         -> tests/golden/C4_subset_X_sensitivity.json
+    python tests/golden/make_sensitivity.py C3_one_step_k2   # about two minutes
+        Phi, Psi of the one step stored in C3_one_step_k2.npz
+        -> tests/golden/C3_one_step_k2_sensitivity.json
 """
 import json
 import os
@@ -22,7 +25,9 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import tatrg  # noqa: E402
-from paper_2412_14104_amd.configs import PRESETS  # noqa: E402
+# the workload presets are plain data; read them without importing the product package
+with open(os.path.join(ROOT, "paper_2412_14104_amd", "presets.json")) as _fh:
+    PRESETS = {k: v for k, v in json.load(_fh).items() if not k.startswith("_")}
 
 NOISE = 1e-15
 NOISE_SEED = 5
@@ -76,9 +81,41 @@ def main_x(name):
                              "step, written by tests/golden/make_sensitivity.py"}, fh, indent=1)
 
 
+def main_one_step(name):
+    """Phi and Psi of one step from the state stored in <name>.npz (make_one_step.py), with
+    1e-15 relative noise added to that state: the deviation from the stored sample of output
+    rows, after the gamma gauge is aligned from Phi (tests/gamma_gauge.py), relative to the
+    stored max |Phi|, max |Psi|."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    from gamma_gauge import align_gamma
+    z = np.load(os.path.join(HERE, name + ".npz"))
+    chi, r, q, seed, k = (int(z[key]) for key in ("chi", "r", "q", "seed", "k"))
+    rng = np.random.default_rng(NOISE_SEED)
+    phi = z["phi_in"] + NOISE * np.abs(z["phi_in"]).max() * rng.standard_normal(
+        z["phi_in"].shape)
+    psi = z["psi_in"] + NOISE * np.abs(z["psi_in"]).max() * rng.standard_normal(
+        z["psi_in"].shape)
+    phi_o, psi_o, _ = tatrg.step(phi, psi, k, chi, r, q, seed)
+    rows = z["rows"]
+    pg, sg, n_live = align_gamma(phi_o.reshape(-1, chi)[rows], psi_o.reshape(-1, chi)[rows],
+                                 z["phi_rows"], z["sigma"])
+    dphi = float(np.abs(pg - z["phi_rows"]).max() / float(z["phi_absmax"]))
+    dpsi = float(np.abs(sg[:, :n_live] - z["psi_rows"][:, :n_live]).max()
+                 / float(z["psi_absmax"]))
+    print(name, "dphi %.2e dpsi %.2e" % (dphi, dpsi), flush=True)
+    with open(os.path.join(HERE, name + "_sensitivity.json"), "w") as fh:
+        json.dump({"case": name, "noise": NOISE, "noise_seed": NOISE_SEED,
+                   "phi_dev": dphi, "psi_dev": dpsi,
+                   "source": "oracle/tatrg.py step() from the stored state with 1e-15 "
+                             "relative noise, written by tests/golden/make_sensitivity.py"},
+                  fh, indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "C3"
     if which.endswith("_subset"):
         main_x(which)
+    elif "_one_step_" in which:
+        main_one_step(which)
     else:
         main(which)

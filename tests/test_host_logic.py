@@ -35,11 +35,48 @@ def test_crossing_none_without_a_crossing_and_exact_hits(scan):
 
 def test_model_flops_contraction_term():
     """The contraction part of the step model is 8 L^2 chi^5 + 4 L chi^5 + 4 L^2 chi^4
-    (two halves of the P and Phi GEMMs and the small brackets); at chi = 32, r = 3 the P and
-    Phi GEMMs alone are 8 L^2 chi^5 = 2.47e12 flops."""
+    + 4 L chi^4 (two halves of the P and Phi GEMMs and the small brackets); at chi = 32,
+    r = 3 the P and Phi GEMMs alone are 8 L^2 chi^5 = 2.47e12 flops and the whole step
+    3.94e12."""
     sys.path.insert(0, ROOT)
     bench = importlib.import_module("bench")
     total, contraction = bench.model_flops_per_step(32, 3, 2)
     L = 96
-    assert contraction == 8 * L * L * 32 ** 5 + 4 * L * 32 ** 5 + 4 * L * L * 32 ** 4
+    assert contraction == (8 * L * L * 32 ** 5 + 4 * L * 32 ** 5 + 4 * L * L * 32 ** 4
+                           + 4 * L * 32 ** 4)
     assert total > contraction > 2.4e12
+    assert 3.9e12 < total < 4.0e12
+    st = bench.stage_model_flops(32, 3, 2)
+    # bond swap: compression 8 chi^7 plus six products of the compressed operand with
+    # chi^3 x 96 panels and their chi^3 x 96 x 96 Grams
+    assert st["S1"] == 8 * 32 ** 7 + 6 * (4 * 32 ** 5 * 96 + 2 * 32 ** 3 * 96 * 96)
+
+
+def test_golden_writers_run_without_the_product_library():
+    """The writers of stored expected values load only oracle/ and the preset data: with any
+    import of the product package made to fail, each module still loads and sees the
+    presets."""
+    import subprocess
+    code = (
+        "import sys, importlib.util\n"
+        "sys.modules['paper_2412_14104_amd'] = None\n"
+        "sys.path.insert(0, %r)\n"
+        "for name in ('make_golden', 'make_scan_golden', 'make_sensitivity'):\n"
+        "    spec = importlib.util.spec_from_file_location(name, %r + '/' + name + '.py')\n"
+        "    mod = importlib.util.module_from_spec(spec)\n"
+        "    spec.loader.exec_module(mod)\n"
+        "    assert mod.PRESETS['C3']['chi'] == 32 and len(mod.PRESETS['C4']['betas']) == 64\n"
+        "assert 'paper_2412_14104_amd.configs' not in sys.modules\n"
+        "print('ok')\n" % (ROOT, os.path.join(HERE, "golden")))
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300)
+    assert res.returncode == 0 and res.stdout.strip() == "ok", res.stderr
+
+
+def test_presets_data_matches_the_workloads():
+    sys.path.insert(0, ROOT)
+    from paper_2412_14104_amd.configs import PRESETS
+    assert PRESETS["C3"] == {**PRESETS["C3"], "chi": 32, "r": 3, "q": 2, "n_steps": 40,
+                             "betas": [0.1496947]}
+    betas = PRESETS["C4"]["betas"]
+    assert betas == [0.140 + 0.020 * i / 63 for i in range(64)]
