@@ -323,13 +323,22 @@ def squeezers(e, f, g, h, ua, ux, uy, ud, lw, q, seed, step, debug=None):
     Pair order: forward (f_mu(n+1), f_mu(n)); backward (b_mu(n+1), b_mu(n)).
     Returns dict mu -> (M[u1,u2,k], N[k,v1,v2], S).
     """
-    chi = e.shape[0]
-    n2 = chi * chi
     # Projected fundamental tensors of the triad cell: A P_A, X sigma P_X, Y P_Y, D P_D.
     ah = ein("iplA,jkp->ijklA", e, ua)
     xh = ein("aplg,jkp->ajklg", f, ux)
     yh = ein("bplg,jkp->bjklg", g, uy)
     dh = ein("iplB,jkp->ijklB", h, ud)
+    return squeezers_of_cell(ah, xh, yh, dh, lw, q, seed, step, debug)
+
+
+def squeezers_of_cell(ah, xh, yh, dh, lw, q, seed, step, debug=None):
+    """Squeezers of a unit cell given by its four fundamental tensors A[f1..f4, a],
+    X sigma[a, f2 f3 f4, g], Y[b, b2 b3 b4, g], D[b1..b4, b] (each possibly projected):
+    the Grams rho_L, rho_R of every mu pair and the optimal pair of squeezer_pair.  The
+    triad cell passes the projected tensors A P_A, X sigma P_X, Y P_Y, D P_D; the plain ATRG
+    cell passes A, X sigma, Y, D themselves."""
+    chi = ah.shape[0]
+    n2 = chi * chi
     # Grams of the two halves of the cell over the swap bond gamma.
     aag = ein("ijklA,ijklB->AB", ah, ah)
     ddg = ein("ijklA,ijklB->AB", dh, dh)

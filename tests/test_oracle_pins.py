@@ -376,3 +376,50 @@ def test_order_parameter_separates_the_phases():
     lo = t.run(0.10, 6, 2, 2, 0, 8)["X_final"]
     hi = t.run(0.20, 6, 2, 2, 0, 8)["X_final"]
     assert abs(lo - 1.0) < 0.15 and abs(hi - 2.0) < 0.05
+
+
+# ----------------------------------------------------------------------------- plain ATRG
+def test_plain_atrg_contraction_follows_its_definition():
+    """atrg.contract (one squeezer at a time) against the defining sum evaluated in one
+    unfactorised einsum, on random tensors at chi = 3."""
+    from oracle import atrg
+    rng = np.random.default_rng(17)
+    chi = 3
+    a, x, y, b = (rng.standard_normal((chi,) * 5) for _ in range(4))
+    sig = rng.random(chi)
+    sq = {mu: (rng.standard_normal((chi,) * 3), rng.standard_normal((chi,) * 3), None)
+          for mu in (2, 3, 4)}
+    phi, psi = atrg.contract(a, x, sig, y, b, sq)
+    m2, m3, m4 = (sq[mu][0] for mu in (2, 3, 4))
+    n2, n3, n4 = (sq[mu][1] for mu in (2, 3, 4))
+    ref_phi = np.einsum("iabcA,Adefg,g,adk,bel,cfm->iklmg", a, x, sig, m2, m3, m4,
+                        optimize=False)
+    ref_psi = np.einsum("jabcB,Bdefg,kda,leb,mfc->jklmg", b, y, n2, n3, n4, optimize=False)
+    assert np.allclose(phi, ref_phi, rtol=1e-13, atol=1e-13 * np.abs(ref_phi).max())
+    assert np.allclose(psi, ref_psi, rtol=1e-13, atol=1e-13 * np.abs(ref_psi).max())
+
+
+@pytest.mark.parametrize("chi,n", [(4, 8), (5, 6), (6, 4)])
+def test_triad_with_r_equal_chi_is_plain_atrg(chi, n):
+    """With r chi = chi^2 internal lines the oversampled isometries are complete unitaries
+    and the triad step is plain ATRG (Section 2, the remark on r = chi; Table 1): f, ln c_k
+    and every spectrum agree to rounding."""
+    from oracle import atrg
+    tr = t.run(BETA_C, chi, chi, 2, 0, n)
+    at = atrg.run(BETA_C, chi, 2, 0, n)
+    assert abs(tr["f"] - at["f"]) <= 1e-12 * abs(at["f"])
+    for st_t, st_a in zip(tr["steps"], at["steps"]):
+        assert abs(st_t["lnc"] - st_a["lnc"]) <= 1e-12
+        for key in ("s", "sigma"):
+            assert np.abs(st_t[key] - st_a[key]).max() <= 1e-12
+        for mu in (2, 3, 4):
+            assert np.abs(st_t["sqz"][mu] - st_a["sqz"][mu]).max() <= 1e-12 * st_a["sqz"][mu][0]
+
+
+def test_triad_with_fewer_internal_lines_truncates():
+    """The identity above is not vacuous: at r = 2 < chi the isometries truncate and f moves
+    at the truncation level."""
+    from oracle import atrg
+    tr = t.run(BETA_C, 6, 2, 2, 0, 4, record=False)
+    at = atrg.run(BETA_C, 6, 2, 0, 4)
+    assert abs(tr["f"] - at["f"]) > 1e-8 * abs(at["f"])
