@@ -91,19 +91,30 @@ tatrg_status tatrg_step(tatrg_handle* h);
  * Gaussian sketch of width w drawn from (seed, step = 0, site), q QR iterations, rank k.
  * d_A: m x n row-major with leading dimension lda >= n (read only).  Outputs (device):
  * d_U m x k, d_S k, d_Vt k x n (all row-major, dense).  Requires 1 <= k <= w <= min(m, n),
- * w <= 96.  Uses the handle's workspace, so m*w and n*w must not exceed chi^4 * L of the
- * handle's configuration.  Asynchronous. */
+ * w <= 96.  Uses the handle's workspace, so m*w and n*w must not exceed chi^4 * Ls of the
+ * handle's configuration (Ls = min(r chi, chi^4), the swap sketch width), and the panel
+ * workspace of the Householder fallback must fit (EINVAL otherwise).  Asynchronous. */
 tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n, int64_t lda,
                         int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
                         double* d_U, double* d_S, double* d_Vt);
 
-/* Synchronising.  h_acc[b], b < batch, receives sum_{j<k} 2^-j ln c_j after k steps. */
+/* Synchronising.  h_acc[b], b < batch, receives the log-norm accumulator
+ * sum_{j<k} 2^-j ln c_j after k steps, where c_j = |T_j|_F is the norm taken out of the
+ * tensor at the canonical form of step j (Section 2, canonical form; Section 3, Z = tTr prod T
+ * on a lattice of 2^k sites, each normalisation of T_j counting for 2^-j of a site).
+ * Returns ENUMERIC when a device-side numerical fault has been flagged (the values are still
+ * copied out). */
 tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc);
 
-/* Synchronising; valid after n_steps steps.  Normalises the last tensor once more and traces
- * it on the 1x1x1x1 periodic lattice:
- *   ln Z / V = sum_{k=0}^{N} 2^-k ln c_k + 2^-N ln tTr,    f = -(ln Z / V) / beta.
- * h_f and h_lnzv (host, `batch` entries each; either may be NULL).  f is NaN at beta = 0. */
+/* Synchronising; valid after n_steps steps (ESTATE otherwise).  The partition function of
+ * the periodic lattice is Z = tTr prod T (Section 3): the last tensor is normalised once more
+ * (c_N) and traced on the 1x1x1x1 periodic lattice, so
+ *   ln Z / V = sum_{k=0}^{N} 2^-k ln c_k + 2^-N ln tTr,    f = -(ln Z / V) / beta
+ * (the free energy per site of Table 2).  The final normalisation works on copies, so the
+ * RG state is left unchanged: a repeated call returns the same values and get_state still
+ * returns the tensor after n_steps steps.  h_f and h_lnzv (host, `batch` entries each;
+ * either may be NULL).  f is NaN at beta = 0.  ENUMERIC when a fault has been flagged
+ * (including a non-positive final trace). */
 tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
 
 /* Synchronising.  Per-step records of temperature b (0 <= b < batch), kept when
@@ -116,7 +127,10 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
  *   of lattice direction 4 open (Section 3, the order parameter of the transition point;
  *   one value).
  * Copies min(cap, chi) values (one for which = 5) to h_out and the count to *n_out.
- * EINVAL without record_spectra, for b, step or which out of range, or cap < 1. */
+ * EINVAL without record_spectra, for b, step or which out of range, or cap < 1.  A flagged
+ * numerical fault is NOT reported here (the call returns OK and copies the records as they
+ * are, so the steps before a fault can be inspected); tatrg_lognorm and tatrg_free_energy
+ * report it. */
 tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,
                               double* h_out, int32_t cap, int32_t* n_out);
 

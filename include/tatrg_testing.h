@@ -76,6 +76,14 @@ int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pas
 int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,
                       uint32_t site, void* stream);
 
+/* Raw Philox4x32-10 output of the counters the sketches use: for t < npairs, pair
+ * p = pair0 + t (elements 2p and 2p + 1 of a sketch) has counter (lo32(p), hi32(p), step,
+ * site) and key (lo32(seed), hi32(seed)); its four output words go to out[4t .. 4t + 3].
+ * out: device, 4 * npairs uint32, 16-byte aligned.  -1 for pair0 < 0, npairs < 1 or a
+ * misaligned out. */
+int tatrg_test_philox_words(uint32_t* out, int64_t pair0, int64_t npairs, uint64_t seed,
+                            uint32_t step, uint32_t site, void* stream);
+
 /* out = permutation of a rank <= 6 row-major tensor; dims and perm are HOST arrays. */
 int tatrg_test_permute(const double* in, double* out, int rank, const int64_t* dims,
                        const int* perm, void* stream);
@@ -95,6 +103,15 @@ struct tatrg_handle;
 int tatrg_profile_enable(struct tatrg_handle* h, int max_launches);
 int tatrg_profile_read(struct tatrg_handle* h, double* total_ms, int32_t* launches,
                        double* flops_per_launch);
+
+/* Stage timing of the profiled steps (tatrg_profile_enable also reserves events at the stage
+ * boundaries of up to ceil(max_launches / 4) steps, on the handle's stream, which the lanes
+ * rejoin before each boundary).  Synchronises; stage_ms[0..5] (host) receives the summed
+ * device time of canonical form (S0, Section 2), bond swap (S1, Eq. (1)), isometries (S2,
+ * Eqs. (2)-(3)), triad tensors (S3, Eqs. (4)-(11)), squeezers (S4) and contraction with the
+ * slot rotation (S5, Eqs. (makeMG)/(makeMH)); *steps the number of steps timed.  Clears the
+ * stage record.  Returns 0, -1 for null arguments, -3 on a HIP error. */
+int tatrg_profile_read_stages(struct tatrg_handle* h, double* stage_ms, int32_t* steps);
 
 #ifdef __cplusplus
 }

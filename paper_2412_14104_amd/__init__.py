@@ -5,7 +5,6 @@ marshalling only.  Every step of the RG runs in the library's HIP kernels; PyTor
 for device memory and the stream.  Importing this package without the built library raises.
 """
 import ctypes
-import math
 import os
 
 __all__ = ["lib", "TatrgConfig", "Engine", "TatrgError", "FP64", "BF16X3", "library_path"]
@@ -82,12 +81,14 @@ _SIGS = {
     "tatrg_test_chol_inv": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _p,
                                             _p]),
     "tatrg_test_philox": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),
+    "tatrg_test_philox_words": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),
     "tatrg_test_permute": (ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.POINTER(_i64),
                                           ctypes.POINTER(ctypes.c_int), _p]),
     "tatrg_test_gauge": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _dbl,
                                         _p]),
     "tatrg_profile_enable": (ctypes.c_int, [_p, ctypes.c_int]),
     "tatrg_profile_read": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32), _dblp]),
+    "tatrg_profile_read_stages": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -189,6 +190,13 @@ class Engine:
                                       ctypes.byref(fl)), self.handle)
         return ms.value, n.value, fl.value
 
+    def profile_read_stages(self):
+        """(summed device ms of stages S0..S5 as a list of six, steps timed)."""
+        ms = (ctypes.c_double * 6)()
+        n = ctypes.c_int32()
+        _check(lib.tatrg_profile_read_stages(self.handle, ms, ctypes.byref(n)), self.handle)
+        return list(ms), n.value
+
     def run(self, beta):
         """All n_steps steps; returns (f, ln Z / V)."""
         self.init(beta)
@@ -203,9 +211,3 @@ def run(beta, chi, r, q, n_steps, seed=0, record_spectra=False):
     f, lnzv = eng.run(beta)
     return {"f": f, "lnZV": lnzv, "engine": eng}
 
-
-def nan_if_zero_beta(beta, value):
-    return float("nan") if beta == 0 else value
-
-
-_ = math

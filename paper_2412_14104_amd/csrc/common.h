@@ -31,7 +31,9 @@ void gemm_f64(const GemmArgs& g, hipStream_t st);
 // Split-bf16 variant: every operand is split x = x0 + x1 + x2 into bf16 planes and the six
 // products with i + j <= 2 are accumulated in fp32 on the bf16 MFMA units.  Same contract.
 // ev_after_split (optional) is recorded on st between the plane splitting and the GEMM.
-void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
+// Returns false, launching nothing, when planes_ws holds fewer than gemm_bf16x3_ws_doubles(g)
+// doubles.
+bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
                  hipStream_t st, hipEvent_t ev_after_split = nullptr);
 // Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes of both operands.
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
@@ -92,6 +94,11 @@ void gauge_rotation(const double* s, const double* P, double* O, int n, int n_pr
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
                      uint64_t seed, uint32_t step, uint32_t site, hipStream_t st,
                      int64_t row_split = 0);
+
+// The generator's four 32-bit output words for counter pairs pair0 .. pair0 + npairs - 1 of
+// (seed, step, site), pair by pair (out holds 4 * npairs words, 16-byte aligned).
+void philox_words(uint32_t* out, int64_t pair0, int64_t npairs, uint64_t seed, uint32_t step,
+                  uint32_t site, hipStream_t st);
 
 // out = permutation of a row-major tensor of rank r <= 6 with dims d: out dim k is input
 // dim perm[k].

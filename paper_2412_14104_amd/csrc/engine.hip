@@ -159,6 +159,7 @@ struct tatrg_handle {
   std::string err;
   int step = 0;
   bool initialized = false;
+  bool host_fault = false;  // a stage could not be enqueued (reported by tatrg_step)
   std::vector<double> betas;
   // buffers
   double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
@@ -181,6 +182,10 @@ struct tatrg_handle {
   bool profile = false;
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
+  // stage boundaries of each profiled step: STAGE_EVENTS events per step on st
+  static constexpr int STAGE_EVENTS = 7;
+  std::vector<hipEvent_t> sev;
+  int sev_used = 0;
   double flops_per_launch = 0.0;
   double *Smat;
   double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
@@ -329,7 +334,9 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->partial = cv.take(h->partial_doubles);
   h->probe = cv.take((size_t)N_PROBES * n4);
   h->trace_part = cv.take(4096);
-  const int64_t w = std::max<int64_t>(Ls, L);
+  // core factors of an RSVD of any width up to MAX_W (the step's widths are L and Ls; the
+  // standalone tatrg_rsvd accepts up to MAX_W)
+  const int64_t w = MAX_W;
   h->s = cv.take(c); h->sig = cv.take(c);
   h->Smat = cv.take(c * c);
   h->Rp = cv.take(c * c); h->Rs = cv.take(c * c); h->Cc = cv.take(c * c);
@@ -382,7 +389,10 @@ void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
   const bool on = h->profile && h->ev_used + 2 <= (int)h->ev.size();
   hipEvent_t e0 = on ? h->ev[h->ev_used] : nullptr;
   if (h->cfg.precision == TATRG_BF16X3) {
-    gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0);
+    if (!gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0)) {
+      h->err = "split-bf16 plane workspace too small for a contraction GEMM";
+      h->host_fault = true;
+    }
   } else {
     if (on) hipEventRecord(e0, h->st);
     gemm_f64(g, h->st);
@@ -990,18 +1000,33 @@ tatrg_status tatrg_step(tatrg_handle* h) {
   for (int b = 0; b < h->cfg.batch; ++b) {
     select_state(h, b);
     double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
+    // stage timing (profiling only): events on the handle's stream, which every lane joins
+    // before the next stage starts
+    const bool timed = h->profile && h->sev_used + tatrg_handle::STAGE_EVENTS <= (int)h->sev.size();
+    auto mark = [&](int i) {
+      if (timed) hipEventRecord(h->sev[h->sev_used + i], h->st);
+    };
     if (rec)
       order_parameter(h->phi, h->psi, h->d.c, open_slot(h->step), h->partial,
                       h->xrec + h->step, h->st);
+    mark(0);
     canonicalize(h, h->step, rec);
+    mark(1);
     bond_swap(h, rec ? rec + h->d.c : nullptr);
+    mark(2);
     isometries(h);
+    mark(3);
     triad(h);
+    mark(4);
     squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
+    mark(5);
     contraction(h);
+    mark(6);
+    if (timed) h->sev_used += tatrg_handle::STAGE_EVENTS;
   }
   select_state(h, 0);
   if (!hip_ok(h, "step")) return TATRG_EHIP;
+  if (h->host_fault) return TATRG_EHIP;
   h->step += 1;
   return TATRG_OK;
 }
@@ -1087,16 +1112,31 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
   }
   const Dims& d = h->d;
   const int nparts = 1024;
+  // The last canonical form runs on copies of Phi and Psi and into a copy of the log-norm
+  // accumulator (ttr[1]), so the state is left as it was: a repeated call returns the same
+  // values and get_state still returns the tensor after n_steps steps.
   for (int b = 0; b < h->cfg.batch; ++b) {
     select_state(h, b);
     double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * d.c : nullptr;
     if (rec)
       order_parameter(h->phi, h->psi, d.c, open_slot(h->step), h->partial, h->xrec + h->step,
                       h->st);
+    copy(h->Xs, h->phi, d.n5, h->st);
+    copy(h->Ys, h->psi, d.n5, h->st);
+    copy(h->ttr + 1, h->acc, 1, h->st);
+    double* const phi = h->phi;
+    double* const psi = h->psi;
+    double* const acc = h->acc;
+    h->phi = h->Xs;
+    h->psi = h->Ys;
+    h->acc = h->ttr + 1;
     canonicalize(h, h->step, rec);
+    h->phi = phi;
+    h->psi = psi;
+    h->acc = acc;
     // tTr = sum_f (A' S' B'^T)[f, f]
-    gemm(h, G(d.n4, d.c, d.c, h->A, d.c, false, h->Smat, d.c, false, h->Xs, d.c));
-    hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->Xs,
+    gemm(h, G(d.n4, d.c, d.c, h->A, d.c, false, h->Smat, d.c, false, h->atf, d.c));
+    hipLaunchKernelGGL(trace_partial_kernel, dim3(nparts), dim3(TPB), 0, h->st, h->atf,
                        (const double*)nullptr, h->B, d.n4, d.c, h->trace_part);
     hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, h->st, h->trace_part, nparts,
                        h->ttr, h->flag);
@@ -1106,11 +1146,13 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
   tatrg_status s = sync_check(h);
   const int N = h->cfg.n_steps;
   for (int b = 0; b < h->cfg.batch; ++b) {
-    double acc = 0.0, ttr = 0.0;
-    hipMemcpy(&acc, h->states[b].acc, sizeof(double), hipMemcpyDeviceToHost);
-    hipMemcpy(&ttr, h->states[b].ttr, sizeof(double), hipMemcpyDeviceToHost);
-    // acc already holds sum_{k=0}^{N} 2^-k ln c_k (the last canonicalisation added c_N)
-    const double lnzv = acc + std::ldexp(std::log(ttr), -N);
+    double t[2] = {0.0, 0.0};
+    if (hipMemcpy(t, h->states[b].ttr, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess) {
+      h->err = "free_energy readback failed";
+      return TATRG_EHIP;
+    }
+    // t[1] = sum_{k=0}^{N} 2^-k ln c_k (the last canonical form added c_N), t[0] = tTr
+    const double lnzv = t[1] + std::ldexp(std::log(t[0]), -N);
     const double beta = h->betas[b];
     if (h_lnzv) h_lnzv[b] = lnzv;
     if (h_f) h_f[b] = (beta > 0.0) ? -lnzv / beta : std::nan("");
@@ -1187,13 +1229,23 @@ const char* tatrg_last_error(const tatrg_handle* h) { return h ? h->err.c_str() 
 int tatrg_profile_enable(tatrg_handle* h, int max_launches) {
   if (!h || max_launches < 0) return -1;
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  for (hipEvent_t e : h->sev) hipEventDestroy(e);
   h->ev.clear();
+  h->sev.clear();
   h->ev_used = 0;
+  h->sev_used = 0;
   h->profile = max_launches > 0;
   for (int i = 0; i < 2 * max_launches; ++i) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -3;
     h->ev.push_back(e);
+  }
+  // stage boundaries for the steps those launches belong to (four contraction GEMMs each)
+  const int steps = (max_launches + 3) / 4;
+  for (int i = 0; i < steps * tatrg_handle::STAGE_EVENTS; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -3;
+    h->sev.push_back(e);
   }
   const double L = h->d.L, c5 = (double)h->d.n5;
   h->flops_per_launch = 2.0 * L * L * c5;  // each of the four contraction GEMMs
@@ -1217,9 +1269,27 @@ int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
   return 0;
 }
 
+int tatrg_profile_read_stages(tatrg_handle* h, double* stage_ms, int32_t* steps) {
+  if (!h || !stage_ms || !steps) return -1;
+  if (hipStreamSynchronize(h->st) != hipSuccess) return -3;
+  constexpr int NS = tatrg_handle::STAGE_EVENTS - 1;
+  for (int j = 0; j < NS; ++j) stage_ms[j] = 0.0;
+  for (int i = 0; i + NS < h->sev_used; i += tatrg_handle::STAGE_EVENTS) {
+    for (int j = 0; j < NS; ++j) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h->sev[i + j], h->sev[i + j + 1]) != hipSuccess) return -3;
+      stage_ms[j] += ms;
+    }
+  }
+  *steps = h->sev_used / tatrg_handle::STAGE_EVENTS;
+  h->sev_used = 0;
+  return 0;
+}
+
 void tatrg_destroy(tatrg_handle* h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  for (hipEvent_t e : h->sev) hipEventDestroy(e);
   for (int z = 0; z < tatrg_handle::N_LANES; ++z) {
     if (h->lane[z].st) {
       hipStreamSynchronize(h->lane[z].st);

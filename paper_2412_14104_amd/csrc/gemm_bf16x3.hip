@@ -254,10 +254,11 @@ size_t gemm_bf16x3_ws_doubles(const GemmArgs& g) {
   return (size_t)((3 * (na + nb) * 2 + 7) / 8 + 64);
 }
 
-void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
+bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
                  hipStream_t st, hipEvent_t ev_after_split) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  (void)planes_ws_doubles;
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return true;
+  // the planes of both operands must fit the workspace: launch nothing otherwise
+  if (!planes_ws || planes_ws_doubles < gemm_bf16x3_ws_doubles(g)) return false;
   const int64_t Kp = kpad(g.K);
   const int64_t ba_n = plane_batches(g, true), bb_n = plane_batches(g, false);
   const int64_t na = ba_n * g.M * Kp, nb = bb_n * g.N * Kp;
@@ -289,6 +290,7 @@ void gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
   if (ev_after_split) (void)hipEventRecord(ev_after_split, st);
   dim3 grid((unsigned)(ba.tiles_m * ba.tiles_n), 1u, (unsigned)g.batch);
   hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(NT), 0, st, ba);
+  return true;
 }
 
 }  // namespace tatrg

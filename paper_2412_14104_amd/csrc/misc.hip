@@ -72,6 +72,24 @@ __global__ void philox_gauss_kernel(double* out, int64_t rows, int64_t cols, int
   }
 }
 
+// Raw output words of the generator for counter pairs pair0 .. pair0 + npairs - 1 (the same
+// counters and key the sketches use): out[4 t + w] = word w of pair pair0 + t.
+__global__ void philox_words_kernel(uint32_t* out, int64_t pair0, int64_t npairs, uint32_t k0,
+                                    uint32_t k1, uint32_t step, uint32_t site) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pr = pair0 + t;
+    uint32_t c[4] = {(uint32_t)pr, (uint32_t)((uint64_t)pr >> 32), step, site};
+    philox10(c, k0, k1);
+    uint4 v;
+    v.x = c[0];
+    v.y = c[1];
+    v.z = c[2];
+    v.w = c[3];
+    reinterpret_cast<uint4*>(out)[t] = v;
+  }
+}
+
 struct PermArgs {
   int rank;
   int64_t out_dims[6];
@@ -309,6 +327,13 @@ void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool t
   hipLaunchKernelGGL(philox_gauss_kernel, dim3(grid_for(npairs)), dim3(TPB), 0, st, out, rows,
                      cols, ld, transposed ? 1 : 0, row_split, (uint32_t)seed,
                      (uint32_t)(seed >> 32), step, site);
+}
+
+void philox_words(uint32_t* out, int64_t pair0, int64_t npairs, uint64_t seed, uint32_t step,
+                  uint32_t site, hipStream_t st) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(philox_words_kernel, dim3(grid_for(npairs)), dim3(TPB), 0, st, out, pair0,
+                     npairs, (uint32_t)seed, (uint32_t)(seed >> 32), step, site);
 }
 
 void permute(const double* in, double* out, int rank, const int64_t* dims, const int* perm,

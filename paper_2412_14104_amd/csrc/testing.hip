@@ -57,7 +57,7 @@ int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t 
                            int64_t sC, double* ws, void* stream) {
   if (!A || !B || !C || !ws || M < 0 || N < 0 || K < 0 || batch < 1) return -1;
   GemmArgs g = mk(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, batch, sA, sB, sC);
-  gemm_bf16x3(g, ws, gemm_bf16x3_ws_doubles(g), (hipStream_t)stream);
+  if (!gemm_bf16x3(g, ws, gemm_bf16x3_ws_doubles(g), (hipStream_t)stream)) return -1;
   return launched();
 }
 
@@ -98,6 +98,13 @@ int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, ui
                       uint32_t site, void* stream) {
   if (!out || rows < 1 || cols < 1) return -1;
   philox_gaussian(out, rows, cols, cols, false, seed, step, site, (hipStream_t)stream);
+  return launched();
+}
+
+int tatrg_test_philox_words(uint32_t* out, int64_t pair0, int64_t npairs, uint64_t seed,
+                            uint32_t step, uint32_t site, void* stream) {
+  if (!out || pair0 < 0 || npairs < 1 || ((uintptr_t)out & 15) != 0) return -1;
+  philox_words(out, pair0, npairs, seed, step, site, (hipStream_t)stream);
   return launched();
 }
 

@@ -101,3 +101,17 @@ def test_record_readback_rejects_bad_indices(pkg):
     assert pkg.lib.tatrg_get_state(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20),
                                    None, None) == -1
     pkg.lib.tatrg_destroy(h)
+
+
+def test_standalone_rsvd_rejects_widths_beyond_the_maximum(pkg):
+    c = cfg(pkg, chi=6, n_steps=4)
+    need = pkg.lib.tatrg_workspace_bytes(ctypes.byref(c))
+    h = ctypes.c_void_p()
+    assert pkg.lib.tatrg_create(ctypes.byref(c), ctypes.c_void_p(1 << 20), need, None,
+                                ctypes.byref(h)) == 0
+    fake = ctypes.c_void_p(1 << 20)
+    # w above 96, w < k, k < 1, lda < n: rejected before any device work
+    for m, n, lda, k, w in ((500, 400, 400, 4, 97), (500, 400, 400, 8, 4),
+                            (500, 400, 400, 0, 4), (500, 400, 300, 4, 8)):
+        assert pkg.lib.tatrg_rsvd(h, fake, m, n, lda, k, w, 1, 0, 0, fake, fake, fake) == -1
+    pkg.lib.tatrg_destroy(h)
