@@ -98,6 +98,19 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
                         int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
                         double* d_U, double* d_S, double* d_Vt);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): tatrg_rsvd without a handle.  Same operation,
+ * arguments and outputs as tatrg_rsvd (with q <= 16), on the stream `stream` (a hipStream_t,
+ * NULL = default), for m, n <= 8192.  Its scratch (panels, factor workspace, partial sums,
+ * flags; 36 MiB) is a static device array of the library, one per device, held until the
+ * process ends; no device or host memory is allocated.  Every call on a device shares that
+ * device's scratch: calls that overlap on one device (two streams, two threads) race, so
+ * order them.  EINVAL for sizes beyond the limits or invalid arguments (nothing launched),
+ * EHIP when the scratch's device address cannot be obtained.  Asynchronous. */
+tatrg_status tatrg_rsvd_noalloc(const double* d_A, int64_t m, int64_t n, int64_t lda,
+                                int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
+                                double* d_U, double* d_S, double* d_Vt, void* stream);
+
 /* Synchronising.  h_acc[b], b < batch, receives the log-norm accumulator
  * sum_{j<k} 2^-j ln c_j after k steps, where c_j = |T_j|_F is the norm taken out of the
  * tensor at the canonical form of step j (Section 2, canonical form; Section 3, Z = tTr prod T

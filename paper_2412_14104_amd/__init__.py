@@ -56,6 +56,8 @@ _SIGS = {
     "tatrg_step": (ctypes.c_int, [_p]),
     "tatrg_rsvd": (ctypes.c_int, [_p, _p, _i64, _i64, _i64, _i32, _i32, _i32, _u64, _u32, _p,
                                   _p, _p]),
+    "tatrg_rsvd_noalloc": (ctypes.c_int, [_p, _i64, _i64, _i64, _i32, _i32, _i32, _u64, _u32,
+                                          _p, _p, _p, _p]),
     "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
     "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
     "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <string>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 namespace tatrg {
@@ -1031,15 +1032,24 @@ tatrg_status tatrg_step(tatrg_handle* h) {
   return TATRG_OK;
 }
 
-tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n, int64_t lda,
-                        int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
-                        double* d_U, double* d_S, double* d_Vt) {
-  if (!h || !d_A || !d_U || !d_S || !d_Vt) return TATRG_EINVAL;
-  if (k < 1 || w < k || w > MAX_W || m < w || n < w || lda < n) return TATRG_EINVAL;
-  const int64_t cap = h->d.n4 * h->d.Ls;
-  if (m * w > cap || n * w > cap) return TATRG_EINVAL;
-  if (tsqr_ws_doubles(m, w) > h->tsqr_cap || tsqr_ws_doubles(n, w) > h->tsqr_cap)
-    return TATRG_EINVAL;
+}  // extern "C"
+
+namespace tatrg {
+// Scratch of tatrg_rsvd_noalloc: a file-scope device array, one copy per device, held until
+// the process ends.  Host code never passes its name to a kernel: the device address comes
+// from hipGetSymbolAddress, once per device, and is cached (noalloc_scratch).
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)36 << 17;  // 36 MiB
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+}  // namespace tatrg
+
+namespace {
+
+// The standalone randomized SVD on the scratch of h (P1, P2, P3, Gq, tsqr_ws, partial, flag and
+// the core factors), shared by tatrg_rsvd and tatrg_rsvd_noalloc.  Arguments are validated by
+// the callers.
+tatrg_status standalone_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n,
+                             int64_t lda, int32_t k, int32_t w, int32_t q, uint64_t seed,
+                             uint32_t site, double* d_U, double* d_S, double* d_Vt) {
   struct MOp : Op {
     tatrg_handle* h;
     const double* A;
@@ -1071,6 +1081,84 @@ tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n
   hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, h->st, d_S, h->Sh, k);
   if (!hip_ok(h, "rsvd")) return TATRG_EHIP;
   return TATRG_OK;
+}
+
+// ---------------------------------------------------------------------------- no-alloc RSVD
+constexpr int64_t NOALLOC_MAX_DIM = 8192;
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this device's scratch (nullptr on a HIP error).
+double* noalloc_scratch(int dev) {
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  return noalloc_ptr[dev];
+}
+
+// Carves the scratch for an m x n problem of width w into a handle that lives on the caller's
+// stack; returns false when it does not fit.
+bool carve_noalloc(tatrg_handle* h, double* base, int64_t m, int64_t n, int w) {
+  Carver cv{reinterpret_cast<char*>(base)};
+  const int64_t mx = std::max(m, n);
+  h->P1 = cv.take((size_t)n * w);
+  h->P2 = cv.take((size_t)m * w);
+  h->P3 = cv.take((size_t)mx * w);
+  h->Gq = cv.take(6 * (size_t)MAX_W * MAX_W);
+  const size_t tq = std::max(tsqr_ws_doubles(m, w), tsqr_ws_doubles(n, w));
+  h->tsqr_ws = cv.take(tq);
+  h->tsqr_cap = tq;
+  h->partial_doubles = 64 * (size_t)MAX_W * MAX_W;
+  h->partial = cv.take(h->partial_doubles);
+  h->flag = reinterpret_cast<int*>(cv.take(8));
+  h->RbT = cv.take((size_t)MAX_W * MAX_W);
+  h->Rb = cv.take((size_t)MAX_W * MAX_W);
+  h->Uh = cv.take((size_t)MAX_W * MAX_W);
+  h->Vh = cv.take((size_t)MAX_W * MAX_W);
+  h->Sh = cv.take(MAX_W);
+  return cv.off <= NOALLOC_SCRATCH_DOUBLES * sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+tatrg_status tatrg_rsvd(tatrg_handle* h, const double* d_A, int64_t m, int64_t n, int64_t lda,
+                        int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
+                        double* d_U, double* d_S, double* d_Vt) {
+  if (!h || !d_A || !d_U || !d_S || !d_Vt) return TATRG_EINVAL;
+  if (k < 1 || w < k || w > MAX_W || m < w || n < w || lda < n || q < 0) return TATRG_EINVAL;
+  const int64_t cap = h->d.n4 * h->d.Ls;
+  if (m * w > cap || n * w > cap) return TATRG_EINVAL;
+  if (tsqr_ws_doubles(m, w) > h->tsqr_cap || tsqr_ws_doubles(n, w) > h->tsqr_cap)
+    return TATRG_EINVAL;
+  return standalone_rsvd(h, d_A, m, n, lda, k, w, q, seed, site, d_U, d_S, d_Vt);
+}
+
+tatrg_status tatrg_rsvd_noalloc(const double* d_A, int64_t m, int64_t n, int64_t lda,
+                                int32_t k, int32_t w, int32_t q, uint64_t seed, uint32_t site,
+                                double* d_U, double* d_S, double* d_Vt, void* stream) {
+  if (!d_A || !d_U || !d_S || !d_Vt) return TATRG_EINVAL;
+  if (k < 1 || w < k || w > MAX_W || m < w || n < w || lda < n || q < 0 || q > 16)
+    return TATRG_EINVAL;
+  if (m > NOALLOC_MAX_DIM || n > NOALLOC_MAX_DIM) return TATRG_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TATRG_EHIP;
+  if (dev >= NOALLOC_MAX_DEVICES) return TATRG_EINVAL;
+  double* base = noalloc_scratch(dev);
+  if (!base) return TATRG_EHIP;
+  // a handle on the stack: its strings and vectors stay empty, so nothing is allocated
+  tatrg_handle h;
+  h.cfg = tatrg_config{};
+  h.st = (hipStream_t)stream;
+  h.lanes = false;
+  if (!carve_noalloc(&h, base, m, n, w)) return TATRG_EINVAL;
+  return standalone_rsvd(&h, d_A, m, n, lda, k, w, q, seed, site, d_U, d_S, d_Vt);
 }
 
 static tatrg_status sync_check(tatrg_handle* h) {
