@@ -153,6 +153,7 @@ def run_path(pkg, torch, precision, chi, r, q, seed, beta, warmup, steps, finish
     k_ms, launches, flops_launch = eng.profile_read()
     stage_ms, stage_steps = eng.profile_read_stages()
     eng.profile_enable(0)
+    swap_paths = [eng.swap_compressed(k) for k in range(warmup + steps)]
     f = lnzv = None
     if finish:
         for _ in range(n_total - warmup - steps):
@@ -161,7 +162,8 @@ def run_path(pkg, torch, precision, chi, r, q, seed, beta, warmup, steps, finish
     out = {"ms_per_step": gpu_ms / steps, "value": steps / (gpu_ms / 1e3), "wall_s": wall,
            "contraction_ms": k_ms, "launches": launches, "flops_per_launch": flops_launch,
            "stage_ms_per_step": [x / max(stage_steps, 1) for x in stage_ms],
-           "n_total": n_total, "f": f, "lnZV": lnzv}
+           "n_total": n_total, "f": f, "lnZV": lnzv,
+           "swap_compressed_timed_steps": sum(1 for p in swap_paths[warmup:] if p == 1)}
     del eng
     return out
 
@@ -274,6 +276,7 @@ def main():
                    "precision": args.precision},
         "roofline": roofline,
         "roofline_fp64_stages": roofline_fp64,
+        "swap_compressed_timed_steps": main_run["swap_compressed_timed_steps"],
         "stages": stage_report,
         "step_model_flops": total_flops,
         "step_model_tflops": total_flops * main_run["value"] / 1e12,

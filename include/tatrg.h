@@ -57,7 +57,11 @@ typedef struct {
   uint64_t seed;          /* Philox4x32-10 key for every Gaussian sketch               */
   int32_t record_spectra; /* nonzero: keep per-step singular spectra and the order
                              parameter X^(m) for readback                               */
-  int32_t reserved;
+  int32_t swap_mode;      /* bond swap: 0 = run the randomized SVD on the compressed cell
+                             middle (QR factors of its two chi^3 x chi^2 panels) whenever
+                             those panels are well enough conditioned, else on the full
+                             middle; 1 = always on the full middle.  Both give the same
+                             result up to rounding (see tatrg_step)                     */
 } tatrg_config;
 
 typedef struct tatrg_handle tatrg_handle;
@@ -78,9 +82,14 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
  * h_betas: host array of `batch` values, each finite and >= 0.  Asynchronous. */
 tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas);
 
-/* One RG step on the device, no host synchronisation: canonical form and normalisation
- * c_k = |T|_F, bond swap by randomized SVD, isometries, triad tensors, squeezers,
- * contraction and slot rotation (Section 2).  With batch = B the step runs for every
+/* One RG step on the device: canonical form and normalisation c_k = |T|_F, bond swap by
+ * randomized SVD, isometries, triad tensors, squeezers, contraction and slot rotation
+ * (Section 2).  With swap_mode = 0 the bond swap factors the two panels of the cell middle
+ * M = sum_x A~_x B~_x^T by a two-pass Cholesky QR and runs the randomized SVD on the
+ * chi^3 x chi^3 middle K between their triangular factors, with the sketch mapped through
+ * the orthonormal factor; the one host synchronisation of the step reads the device's
+ * verdict on the panels' conditioning, and ill-conditioned panels (the first steps, beta = 0)
+ * take the full middle instead.  With swap_mode = 1 no host synchronisation happens.  With batch = B the step runs for every
  * temperature in turn; all temperatures share the same Gaussian sketches (common random
  * numbers), so entry b of a batch equals a batch-1 run at beta_b bit for bit.  With
  * record_spectra it first records X^(k) of the incoming tensor (see tatrg_get_record).
@@ -135,12 +144,14 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
  * tatrg_free_energy):
  *   which = 0: canonical s (chi values), 1: swap sigma (chi), 2/3/4: squeezer S of
  *   direction mu = 2/3/4 (chi);
+ *   which = 6: the bond swap's path at that step: 1 (compressed middle), 0 (full middle),
+ *   -1 (not run yet); available without record_spectra, no synchronisation;
  *   which = 5: the order parameter X^(step) = (Tr A)^2 / Tr A^2 of the incoming tensor, with
  *   A_kl = T summed over the forward = backward legs of three directions and the legs k, l
  *   of lattice direction 4 open (Section 3, the order parameter of the transition point;
  *   one value).
- * Copies min(cap, chi) values (one for which = 5) to h_out and the count to *n_out.
- * EINVAL without record_spectra, for b, step or which out of range, or cap < 1.  A flagged
+ * Copies min(cap, chi) values (one for which = 5, 6) to h_out and the count to *n_out.
+ * EINVAL without record_spectra (which < 6), for b, step or which out of range, or cap < 1.  A flagged
  * numerical fault is NOT reported here (the call returns OK and copies the records as they
  * are, so the steps before a fault can be inspected); tatrg_lognorm and tatrg_free_energy
  * report it. */

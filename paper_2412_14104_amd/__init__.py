@@ -41,7 +41,7 @@ class TatrgConfig(ctypes.Structure):
     _fields_ = [("chi", ctypes.c_int32), ("r", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("record_spectra", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("record_spectra", ctypes.c_int32), ("swap_mode", ctypes.c_int32)]
 
 
 _p = ctypes.c_void_p
@@ -114,11 +114,12 @@ class Engine:
     current stream unless one is given."""
 
     def __init__(self, chi, r, q, n_steps, seed=0, precision=FP64, record_spectra=True,
-                 stream=None, device="cuda", batch=1):
+                 stream=None, device="cuda", batch=1, swap_mode=0):
         import torch
         self.cfg = TatrgConfig(chi=chi, r=r, q=q, n_steps=n_steps, batch=batch,
                                precision=precision, seed=seed,
-                               record_spectra=1 if record_spectra else 0, reserved=0)
+                               record_spectra=1 if record_spectra else 0,
+                               swap_mode=swap_mode)
         nbytes = lib.tatrg_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise TatrgError(-1, "invalid configuration")
@@ -131,7 +132,7 @@ class Engine:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:  # lib is None at interpreter exit
             lib.tatrg_destroy(h)
             self.handle = None
 
@@ -166,6 +167,15 @@ class Engine:
         _check(lib.tatrg_get_record(self.handle, b, step, which, buf, self.chi,
                                     ctypes.byref(n)), self.handle)
         return [buf[i] for i in range(n.value)]
+
+    def swap_compressed(self, step, b=0):
+        """1 when the bond swap of `step` ran on the compressed cell middle, 0 on the full
+        one, -1 when the step has not run."""
+        buf = (ctypes.c_double * 1)()
+        n = ctypes.c_int32()
+        _check(lib.tatrg_get_record(self.handle, b, step, 6, buf, 1, ctypes.byref(n)),
+               self.handle)
+        return int(buf[0])
 
     def order_parameter(self, step, b=0):
         """X^(step) of temperature b (recorded with record_spectra)."""

@@ -67,6 +67,19 @@ void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hi
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
               hipStream_t st, double shift_coef = 0.0);
 
+// Solves X L^T = B in place for `batch` tall panels X (m x n, leading dim ldx, stride sX)
+// with lower-triangular L (n x n, stride sL): column blocks of 64, each a GEMM update by the
+// blocks before it and a forward substitution per row against the diagonal block.
+void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int n, int batch,
+                        int64_t sX, int64_t sL, hipStream_t st);
+
+// Checks the diagonal of `batch` lower Cholesky factors (n x n, stride n*n): *flag = 1 when a
+// diagonal entry is not finite or not positive, when the smallest pivot L_ii^2 is below
+// min_ratio times the largest, or when a pivot leaves (lo, hi).  Leaves *flag alone
+// otherwise.
+void chol_check(const double* L, int n, int batch, double min_ratio, double lo, double hi,
+                int* flag, hipStream_t st);
+
 // ---------------------------------------------------------------------------- small dense
 // One-sided Jacobi SVD of `batch` square n x n matrices (n <= 96): A = U diag(S) V^T with S
 // descending.  A (read only), U, V row-major n x n, strides n*n; S stride n.  Columns of U

@@ -168,6 +168,13 @@ struct tatrg_handle {
   double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm2, *pm3, *sq1, *sq2, *sq3, *sq4;
   double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
   double *partial, *probe, *small, *planes;
+  // compressed cell middle of the bond swap: the two panels [f'][(x beta)], [b'][(x alpha)]
+  // (cp, stride n5), their orthonormal factors (cq), the Cholesky factors of the two passes
+  // (cg, cg2), T = L1 L2 = R^T (ct) and R_A (cra); cflag (device) and hflag (pinned host)
+  // carry the conditioning verdict
+  double *cp, *cq, *cg, *cg2, *ctt, *ct, *cra;
+  int* cflag = nullptr;
+  int* hflag = nullptr;
   size_t planes_doubles;
   int* flag;
   double* acc;
@@ -212,6 +219,7 @@ struct tatrg_handle {
     double *phi = nullptr, *psi = nullptr, *acc = nullptr, *lnc = nullptr;
     double *spectra = nullptr, *xrec = nullptr, *ttr = nullptr;
     int* flag = nullptr;
+    std::vector<signed char> swap_compressed;  // per step: 1 compressed middle, 0 full, -1 not run
   };
   std::vector<State> states;
   hipEvent_t fork = nullptr;
@@ -237,6 +245,7 @@ bool valid(const tatrg_config* c) {
   if (c->n_steps < 1 || c->n_steps > 64) return false;
   if (c->batch < 1 || c->batch > MAX_BATCH) return false;
   if (c->precision != TATRG_FP64 && c->precision != TATRG_BF16X3) return false;
+  if (c->swap_mode != 0 && c->swap_mode != 1) return false;
   const int64_t L = std::min<int64_t>((int64_t)c->r * c->chi, (int64_t)c->chi * c->chi);
   if (L > MAX_W) return false;
   return true;
@@ -287,11 +296,19 @@ void carve(tatrg_handle* h, Carver& cv) {
     st.spectra = cv.take((size_t)(h->cfg.n_steps + 1) * 5 * c);
     st.xrec = cv.take((size_t)h->cfg.n_steps + 1);
     st.ttr = cv.take(8);
+    if (cv.base) st.swap_compressed.assign((size_t)h->cfg.n_steps + 1, -1);
   }
   select_state(h, 0);
   h->A = cv.take(n5); h->B = cv.take(n5);
   h->X = cv.take(n5); h->Y = cv.take(n5);
-  h->atf = cv.take(n5); h->btx = cv.take(n5);
+  h->cp = cv.take(2 * n5);
+  h->atf = cv.take(n5);
+  h->btx = cv.take(n5);
+  h->cq = cv.take(2 * n5);
+  h->cg = cv.take(2 * n2 * n2); h->cg2 = cv.take(2 * n2 * n2); h->ct = cv.take(2 * n2 * n2);
+  h->ctt = cv.take(2 * n2 * n2);
+  h->cra = cv.take(n2 * n2);
+  h->cflag = (int*)cv.take(8);
   h->P1 = cv.take(n4 * Ls); h->P2 = cv.take(n4 * Ls);
   h->P3 = cv.take(n4 * std::max(Ls, c));
   h->Gq = cv.take(6 * (int64_t)MAX_W * MAX_W);
@@ -532,11 +549,13 @@ struct Op {
 // Randomized SVD (Gaussian sketch, q QR iterations): on return Pa (m x w) holds Q and Pb
 // (n x w) holds Qb; Uh, S, Vh (w x w) are the core SVD of Rb^T, so that
 // Op ~= (Q Uh) S (Qb Vh)^T.  range_only stops after the last orthonormalisation of Pa.
+// sketch_given: Pb already holds the sketch (n x w) instead of a fresh Philox draw.
 void rsvd(tatrg_handle* h, Op& op, int64_t m, int64_t n, int w, int q, uint32_t site,
-          double* Pa, double* Pb, bool range_only, bool try_cholqr) {
+          double* Pa, double* Pb, bool range_only, bool try_cholqr, bool sketch_given = false) {
   hipStream_t st = h->st;
-  philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st,
-                  op.right_split);
+  if (!sketch_given)
+    philox_gaussian(Pb, n, w, w, false, h->cfg.seed, (uint32_t)h->step, site, st,
+                    op.right_split);
   op.apply(Pb, Pa, w);
   orth(h, Pa, m, w, w, nullptr, try_cholqr);
   for (int it = 0; it < h->cfg.q; ++it) {
@@ -554,28 +573,32 @@ void rsvd(tatrg_handle* h, Op& op, int64_t m, int64_t n, int w, int q, uint32_t 
   jacobi_svd(h->RbT, h->Uh, h->Sh, h->Vh, w, 1, st);
 }
 
-// Cell middle of the swap: M[(alpha,f'),(beta,b')] = sum_x s_a B[x,b',a] A[x,f',b] s_b, rows
-// stored in (f', alpha) order, columns (right-space panels) in (b', beta) order, so that
-// every product is one GEMM with N = chi * w.
+// Cell middle of the swap as a product of two factors over the inner bond x:
+//   M[(p,alpha),(p',beta)] = sum_x fa[p, (x beta)] fb[(x alpha), p'],
+// fa: na x chi^2, fb: chi^2 x nb.  The full middle has fa = A~ as [f'][(x beta)] and
+// fb = B~ as [(x alpha)][b'] (na = nb = chi^3); the compressed one has fa = R_A and fb = R_B^T
+// (na = nb = chi^2).  Rows of the left-space panels are (p, alpha), those of the right-space
+// panels (p', beta), p-major, so that every product is one GEMM with N = chi * w.
 struct SwapOp : Op {
   tatrg_handle* h;
+  const double* fa = nullptr;
+  const double* fb = nullptr;
+  int64_t na = 0, nb = 0;
   void apply(const double* om, double* y, int w) override {
     const Dims& d = h->d;
-    // t1[(x alpha), (beta j)] = btx[(x alpha), b'] om[b', (beta j)]   (long K: split)
-    gemm_long_k(h, G(d.n2, d.c * w, d.n3, h->btx, d.n3, false, om, d.c * w, false, h->t1,
-                     d.c * w));
+    // t1[(x alpha), (beta j)] = fb[(x alpha), p'] om[p', (beta j)]
+    gemm_long_k(h, G(d.n2, d.c * w, nb, fb, nb, false, om, d.c * w, false, h->t1, d.c * w));
     perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {0, 2, 1, 3});  // [x, beta, alpha, j]
-    // y[f', (alpha j)] = atf[f', (x beta)] t2[(x beta), (alpha j)]
-    gemm(h, G(d.n3, d.c * w, d.n2, h->atf, d.n2, false, h->t2, d.c * w, false, y, d.c * w));
+    // y[p, (alpha j)] = fa[p, (x beta)] t2[(x beta), (alpha j)]
+    gemm_long_k(h, G(na, d.c * w, d.n2, fa, d.n2, false, h->t2, d.c * w, false, y, d.c * w));
   }
   void apply_t(const double* qm, double* z, int w) override {
     const Dims& d = h->d;
-    // t1[(x beta), (alpha j)] = atf^T qm[f', (alpha j)]   (long K: split)
-    gemm_long_k(h, G(d.n2, d.c * w, d.n3, h->atf, d.n2, true, qm, d.c * w, false, h->t1,
-                     d.c * w));
+    // t1[(x beta), (alpha j)] = fa^T qm[p, (alpha j)]
+    gemm_long_k(h, G(d.n2, d.c * w, na, fa, d.n2, true, qm, d.c * w, false, h->t1, d.c * w));
     perm(h, h->t1, h->t2, {d.c, d.c, d.c, w}, {0, 2, 1, 3});  // [x, alpha, beta, j]
-    // z[b', (beta j)] = btx^T[b', (x alpha)] t2[(x alpha), (beta j)]
-    gemm(h, G(d.n3, d.c * w, d.n2, h->btx, d.n3, true, h->t2, d.c * w, false, z, d.c * w));
+    // z[p', (beta j)] = fb^T[p', (x alpha)] t2[(x alpha), (beta j)]
+    gemm_long_k(h, G(nb, d.c * w, d.n2, fb, nb, true, h->t2, d.c * w, false, z, d.c * w));
   }
 };
 
@@ -617,27 +640,123 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
   hipLaunchKernelGGL(smat_kernel, dim3(1), dim3(256), 0, st, h->Oc, h->s, h->Smat, c);
 }
 
-void bond_swap(tatrg_handle* h, double* rec) {
+// Orthonormal factors of the two swap panels, the canonical isometries reshaped as
+// P_A[f', (x g)] = A'[x, f', g] and P_B[b', (x g)] = B'[x, b', g] (chi^3 x chi^2 each, stored
+// in cp with stride n5, batched): CholeskyQR2 (two passes of Gram, Cholesky and triangular
+// solve), P = Q R^ with R^ = L2^T L1^T.  The cell middle's panels are P (1 x S'), with the
+// gauge-rotated weights S' of the canonical form on the g index, so its factors are
+// R = R^ (1 x S'); the isometries are far better conditioned than the weighted panels, whose
+// condition grows like 1 / s_min.  Writes Q to cq, R_A = (L1 L2)^T (1 x S') to cra and
+// R_B^T = (1 x S') L1 L2 to ct + chi^4.  cflag is raised when a pivot of the first pass is
+// below 1e-15 of the largest (condition beyond ~3e7, where two passes no longer give an
+// orthonormal Q to rounding; also every rank-deficient panel, as in the first steps or at
+// beta = 0) or a pivot of the second pass leaves (0.5, 2).
+void compress_swap_panels(tatrg_handle* h) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
+  zero((double*)h->cflag, 1, st);
+  gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
+  cholesky_shifted(h->cg, (int)n2, 2, 0.0, h->cflag, st);
+  chol_check(h->cg, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st);
+  copy(h->cq, h->cp, 2 * n5, st);
+  trsm_right_lower_t(h->cq, n2, n3, h->cg, (int)n2, 2, n5, s2, st);
+  gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
+  cholesky_shifted(h->cg2, (int)n2, 2, 0.0, h->cflag, st);
+  chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st);
+  trsm_right_lower_t(h->cq, n2, n3, h->cg2, (int)n2, 2, n5, s2, st);
+  // ctt = L1 L2 = R^^T, rows (x g); ct[(x b)] = sum_g S'[b, g] ctt[(x g)] (S' is symmetric)
+  gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ctt, n2), 2, s2, s2, s2));
+  gemm(h, Gb(G(c, n2, c, h->Smat, c, false, h->ctt, n2, false, h->ct, n2), 2 * c, 0, c * n2,
+             c * n2));
+  transpose_batched(h->ct, h->cra, (int)n2, (int)n2, 1, st);
+}
+
+// Whether the compressed middle may be used: one host round trip for the device verdict.
+bool compression_ok(tatrg_handle* h) {
+  int v = 1;
+  if (h->hflag) {
+    if (hipMemcpyAsync(h->hflag, h->cflag, sizeof(int), hipMemcpyDeviceToHost, h->st) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->st) != hipSuccess) {
+      h->host_fault = true;
+      h->err = "bond swap: reading the compression verdict failed";
+      return false;
+    }
+    v = *h->hflag;
+  } else if (hipMemcpy(&v, h->cflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+    h->host_fault = true;
+    h->err = "bond swap: reading the compression verdict failed";
+    return false;
+  }
+  return v == 0;
+}
+
+// Bond swap (Section 2, Eq. (1)): rank-chi randomized SVD of the cell middle M, which gives
+// X, sigma, Y.  M = (Q_A x 1)(K)(Q_B x 1)^T with the panels' QR factors P = Q R and
+// K[(p,alpha),(p',beta)] = sum_x R_A[p,(x beta)] R_B[p',(x alpha)] (chi^3 x chi^3): with Q_A,
+// Q_B orthonormal, the randomized SVD of M with the sketch Omega is the one of K with the
+// sketch (Q_B x 1)^T Omega, lifted back by Q_A and Q_B, and each product with K costs
+// 4 chi^5 Ls instead of 4 chi^6 Ls (Table 1 prices bond swapping at O(q r chi^6)).  When the
+// panels are too ill-conditioned for that (compress_swap_panels), or with swap_mode = 1, the
+// products run on the full middle instead; both give the same X, sigma, Y up to rounding.
+// Returns whether the compressed middle was used.
+bool bond_swap(tatrg_handle* h, double* rec) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int c = d.c;
   const int w = d.Ls;
-  // A~ = A' S', B~ = B' S'; atf = [f', (x beta)], btx = [(x alpha), b']
-  gemm(h, G(d.n4, c, c, h->A, c, false, h->Smat, c, false, h->Xs, c));
-  gemm(h, G(d.n4, c, c, h->B, c, false, h->Smat, c, false, h->Ys, c));
-  perm(h, h->Xs, h->atf, {c, d.n3, c}, {1, 0, 2});
-  perm(h, h->Ys, h->btx, {c, d.n3, c}, {0, 2, 1});
+  bool compressed = false;
+  if (h->cfg.swap_mode == 0) {
+    // P_A = [f', (x g)] and P_B = [b', (x g)] from A' and B'
+    perm(h, h->A, h->cp, {c, d.n3, c}, {1, 0, 2});
+    perm(h, h->B, h->cp + d.n5, {c, d.n3, c}, {1, 0, 2});
+    compress_swap_panels(h);
+    compressed = compression_ok(h);
+  }
   SwapOp op;
   op.h = h;
-  op.right_split = d.n3;  // sketch rows (beta, b') stored in (b', beta) order
-  rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true);
-  // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c] (Qb rows in (b', beta))
-  gemm(h, G(d.n4, c, w, h->P2, w, false, h->Uh, w, false, h->Xs, c));
-  perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
-  gemm(h, G(d.n4, c, w, h->P1, w, false, h->Vh, w, false, h->Xs, c));
-  perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
+  if (compressed) {
+    const double* QA = h->cq;
+    const double* QB = h->cq + d.n5;
+    // the sketch of M, rows (beta, b') stored in (b', beta) order, then (Q_B x 1)^T Omega:
+    // rows (p', beta)
+    philox_gaussian(h->P2, d.n4, w, w, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
+                    d.n3);
+    gemm_long_k(h, G(d.n2, c * w, d.n3, QB, d.n2, true, h->P2, c * w, false, h->P1, c * w));
+    op.fa = h->cra;               // R_A
+    op.na = d.n2;
+    op.fb = h->ct + d.n2 * d.n2;  // R_B^T
+    op.nb = d.n2;
+    rsvd(h, op, d.n3, d.n3, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true, true);
+    // U~ = Q Uh[:, :c] as [p][(alpha g)]; X rows (f', alpha) = Q_A U~
+    gemm(h, G(d.n3, c, w, h->P2, w, false, h->Uh, w, false, h->t1, c));
+    gemm(h, G(d.n3, d.n2, d.n2, QA, d.n2, false, h->t1, d.n2, false, h->Xs, d.n2));
+    perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
+    gemm(h, G(d.n3, c, w, h->P1, w, false, h->Vh, w, false, h->t1, c));
+    gemm(h, G(d.n3, d.n2, d.n2, QB, d.n2, false, h->t1, d.n2, false, h->Xs, d.n2));
+    perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
+  } else {
+    // A~ = A' S', B~ = B' S'; atf = [f', (x beta)], btx = [(x alpha), b']
+    gemm(h, G(d.n4, c, c, h->A, c, false, h->Smat, c, false, h->Xs, c));
+    gemm(h, G(d.n4, c, c, h->B, c, false, h->Smat, c, false, h->Ys, c));
+    perm(h, h->Xs, h->atf, {c, d.n3, c}, {1, 0, 2});
+    perm(h, h->Ys, h->btx, {c, d.n3, c}, {0, 2, 1});
+    op.fa = h->atf;
+    op.na = d.n3;
+    op.fb = h->btx;
+    op.nb = d.n3;
+    op.right_split = d.n3;  // sketch rows (beta, b') stored in (b', beta) order
+    rsvd(h, op, d.n4, d.n4, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true);
+    // X rows (f', alpha) = Q Uh[:, :c]; Y rows (beta, b') = Qb Vh[:, :c] (Qb rows in (b', beta))
+    gemm(h, G(d.n4, c, w, h->P2, w, false, h->Uh, w, false, h->Xs, c));
+    perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
+    gemm(h, G(d.n4, c, w, h->P1, w, false, h->Vh, w, false, h->Xs, c));
+    perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
+  }
   hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, h->sig, h->Sh, c);
   if (rec) hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec, h->Sh, c);
+  return compressed;
 }
 
 // Gram of the (l2 l3) pair: rho[(l2 l3),(l2' l3')] = sum over the other legs of T T' for
@@ -952,6 +1071,8 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
          hipEventCreateWithFlags(&h->lane[z].done, hipEventDisableTiming) == hipSuccess;
   }
   h->lanes = ok;
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, 64, hipHostMallocDefault) == hipSuccess) h->hflag = (int*)hp;
   (void)hipGetLastError();
   *out = h;
   return TATRG_OK;
@@ -1013,7 +1134,9 @@ tatrg_status tatrg_step(tatrg_handle* h) {
     mark(0);
     canonicalize(h, h->step, rec);
     mark(1);
-    bond_swap(h, rec ? rec + h->d.c : nullptr);
+    const bool comp = bond_swap(h, rec ? rec + h->d.c : nullptr);
+    if (h->step < (int)h->states[b].swap_compressed.size())
+      h->states[b].swap_compressed[h->step] = comp ? 1 : 0;
     mark(2);
     isometries(h);
     mark(3);
@@ -1251,11 +1374,17 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
 tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,
                               double* h_out, int32_t cap, int32_t* n_out) {
   if (!h || !h_out || !n_out || cap < 1) return TATRG_EINVAL;
-  if (!h->cfg.record_spectra || b < 0 || b >= h->cfg.batch || step < 0 ||
-      step > h->cfg.n_steps || which < 0 || which > 5)
+  if (b < 0 || b >= h->cfg.batch || step < 0 || step > h->cfg.n_steps || which < 0 ||
+      which > 6 || (which < 6 && !h->cfg.record_spectra))
     return TATRG_EINVAL;
-  tatrg_status s = sync_check(h);
   const tatrg_handle::State& st = h->states[b];
+  if (which == 6) {  // host-side record, no synchronisation
+    const int v = step < (int)st.swap_compressed.size() ? st.swap_compressed[step] : -1;
+    h_out[0] = (double)v;
+    *n_out = 1;
+    return TATRG_OK;
+  }
+  tatrg_status s = sync_check(h);
   int n = 1;
   if (which == 5) {
     hipMemcpy(h_out, st.xrec + step, sizeof(double), hipMemcpyDeviceToHost);
@@ -1386,6 +1515,7 @@ void tatrg_destroy(tatrg_handle* h) {
     if (h->lane[z].done) hipEventDestroy(h->lane[z].done);
   }
   if (h->fork) hipEventDestroy(h->fork);
+  if (h->hflag) hipHostFree(h->hflag);
   delete h;
 }
 

@@ -734,6 +734,111 @@ void set_lds_attr(const void* fn) {
                       LDS_DOUBLES * (int)sizeof(double));
 }
 
+// Rows of X[:, j:j+jb] solved against the diagonal block L_jj: x L_jj^T = b for every row (a
+// forward substitution, one row per thread held in registers; the block of L in LDS).
+__global__ __launch_bounds__(64) void trsm_diag_kernel(double* Xall, int64_t ldx, int64_t m,
+                                                       int64_t sX, const double* Lall, int n,
+                                                       int64_t sL, int j, int jb) {
+  __shared__ double D[64][65];
+  const double* L = Lall + (int64_t)blockIdx.y * sL;
+  double* X = Xall + (int64_t)blockIdx.y * sX;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < jb * jb; idx += 64) {
+    const int r = idx / jb, c = idx - (idx / jb) * jb;
+    D[r][c] = L[(int64_t)(j + r) * n + j + c];
+  }
+  __syncthreads();
+  const int64_t row_i = (int64_t)blockIdx.x * 64 + tid;
+  if (row_i >= m) return;
+  double* row = X + row_i * ldx + j;
+  double x[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) x[c] = (c < jb) ? row[c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    if (c < jb) {
+      double s = x[c];
+#pragma unroll
+      for (int l = 0; l < c; ++l) s -= x[l] * D[c][l];
+      x[c] = s / D[c][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 64; ++c)
+    if (c < jb) row[c] = x[c];
+}
+
+// Diagonal of each lower factor: raises *flag when an entry is not finite or not positive,
+// when min d_i / max d_i < min_ratio (d_i = L_ii^2, the pivots), or when a pivot leaves
+// (lo, hi) (lo = 0, hi = inf disable that test).
+__global__ __launch_bounds__(256) void chol_check_kernel(const double* Lall, int n, int64_t sL,
+                                                         double min_ratio, double lo, double hi,
+                                                         int* flag) {
+  const double* L = Lall + (int64_t)blockIdx.x * sL;
+  __shared__ double mn[256], mx[256];
+  __shared__ int bad[256];
+  double a = INFINITY, b = 0.0;
+  int f = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double l = L[(int64_t)i * n + i];
+    const double d = l * l;
+    if (!(l > 0.0) || !isfinite(l) || !(d > lo) || !(d < hi)) f = 1;
+    a = fmin(a, d);
+    b = fmax(b, d);
+  }
+  mn[threadIdx.x] = a;
+  mx[threadIdx.x] = b;
+  bad[threadIdx.x] = f;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + o]);
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+      bad[threadIdx.x] |= bad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && (bad[0] || !(mn[0] >= min_ratio * mx[0]))) flag[0] = 1;
+}
+
+void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int n, int batch,
+                        int64_t sX, int64_t sL, hipStream_t st) {
+  const int nbk = 64;
+  for (int j = 0; j < n; j += nbk) {
+    const int jb = (n - j) < nbk ? (n - j) : nbk;
+    if (j > 0) {
+      // X[:, j:j+jb] -= X[:, 0:j] L[j:j+jb, 0:j]^T
+      GemmArgs g;
+      g.M = m;
+      g.N = jb;
+      g.K = j;
+      g.A = X;
+      g.lda = ldx;
+      g.sA = sX;
+      g.ta = false;
+      g.B = L + (int64_t)j * n;
+      g.ldb = n;
+      g.sB = sL;
+      g.tb = true;
+      g.C = X + j;
+      g.ldc = ldx;
+      g.sC = sX;
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      g.batch = batch;
+      gemm_f64(g, st);
+    }
+    hipLaunchKernelGGL(trsm_diag_kernel, dim3((unsigned)((m + 63) / 64), batch), dim3(64), 0,
+                       st, X, ldx, m, sX, L, n, sL, j, jb);
+  }
+}
+
+void chol_check(const double* L, int n, int batch, double min_ratio, double lo, double hi,
+                int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(chol_check_kernel, dim3(batch), dim3(256), 0, st, L, n, (int64_t)n * n,
+                     min_ratio, lo, hi, flag);
+}
+
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
               hipStream_t st, double shift_coef) {
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, R, Rinv, n, pass, fail,

@@ -32,14 +32,14 @@ def test_every_declared_symbol_is_exported(pkg):
 
 def cfg(pkg, **kw):
     base = dict(chi=16, r=2, q=2, n_steps=40, batch=1, precision=0, seed=0, record_spectra=1,
-                reserved=0)
+                swap_mode=0)
     base.update(kw)
     return pkg.TatrgConfig(**base)
 
 
 @pytest.mark.parametrize("bad", [dict(chi=1), dict(r=0), dict(q=-1), dict(n_steps=0),
                                  dict(n_steps=65), dict(batch=0), dict(batch=1025),
-                                 dict(precision=7),
+                                 dict(precision=7), dict(swap_mode=2),
                                  dict(chi=64, r=2)])
 def test_invalid_configurations_are_rejected(pkg, bad):
     c = cfg(pkg, **bad)
@@ -95,8 +95,11 @@ def test_record_readback_rejects_bad_indices(pkg):
                                 ctypes.byref(h)) == 0
     buf = (ctypes.c_double * 6)()
     n = ctypes.c_int32()
-    for b, step, which in ((2, 0, 0), (-1, 0, 0), (0, 5, 0), (0, 0, 6), (0, -1, 5)):
+    for b, step, which in ((2, 0, 0), (-1, 0, 0), (0, 5, 0), (0, 0, 7), (0, -1, 5), (2, 0, 6)):
         assert pkg.lib.tatrg_get_record(h, b, step, which, buf, 6, ctypes.byref(n)) == -1
+    # the swap-path record is host-side: -1 before the step has run, no device access
+    assert pkg.lib.tatrg_get_record(h, 1, 2, 6, buf, 6, ctypes.byref(n)) == 0
+    assert n.value == 1 and buf[0] == -1.0
     # checkpointing is for batch 1 only
     assert pkg.lib.tatrg_get_state(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20),
                                    None, None) == -1

@@ -201,3 +201,36 @@ def test_checkpoint_and_resume_is_exact(pkg):
         b.step()
     f_b, l_b = b.free_energy()
     assert f_b == f_full and l_b == l_full, (f_b, f_full)
+
+
+def test_compressed_and_full_cell_middle_agree(pkg):
+    """The bond swap's randomized SVD on the compressed middle K (QR factors of the two cell
+    panels) and on the full middle M give the same run up to rounding (Section 2, Eq. (1)):
+    chi = 16, r = 2, 40 steps, both against the oracle's stored spectra, and the compressed
+    middle is taken while the panels are well conditioned: not in the first steps (zero
+    padding leaves them rank deficient) nor once the flow nears its low-rank fixed point
+    (from step 25 on at chi = 16), but in between."""
+    g = golden("C2")
+    run = g["runs"][0]
+    res = {}
+    for mode in (0, 1):
+        eng = pkg.Engine(g["chi"], g["r"], g["q"], g["n_steps"], seed=g["seed"], swap_mode=mode)
+        res[mode] = eng.run(run["beta"])[0]
+        compare_spectra(eng, run["steps"], g["n_steps"], "C2 swap_mode %d" % mode)
+        paths = [eng.swap_compressed(k) for k in range(g["n_steps"])]
+        print("swap_mode", mode, "compressed steps:", "".join(str(p) for p in paths),
+              flush=True)
+        if mode == 1:
+            assert not any(paths)
+        else:
+            assert paths[0] == 0 and all(paths[8:20]), paths
+    assert abs(res[0] - res[1]) <= 1e-12 * abs(res[1]), res
+
+
+def test_beta_zero_takes_the_full_cell_middle(pkg):
+    """At beta = 0 the tensor stays rank one, the swap panels are rank deficient at every
+    step and the swap runs on the full middle; ln Z / V = ln 2 regardless."""
+    eng = pkg.Engine(6, 2, 2, 8)
+    _, lnzv = eng.run(0.0)
+    assert abs(lnzv - math.log(2.0)) < 1e-14
+    assert all(eng.swap_compressed(k) == 0 for k in range(8))
