@@ -62,6 +62,14 @@ int tatrg_test_svd(const double* A, double* U, double* S, double* V, int n, int 
 int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag,
                         void* stream);
 
+/* Blocked Cholesky with inverse of `batch` SPD n x n matrices A (stride n*n), the
+ * factorisation of the bond swap's panel Grams and of the squeezer Grams: A <- L (lower,
+ * zeros above) with A = L L^T; Dinv receives the inverses of L's 64 x 64 diagonal blocks
+ * (batch x ceil(n / 64) x 64 x 64 doubles) and Linv (batch x n x n) the full inverse L^{-1};
+ * T is scratch of n * n / 2 doubles.  A pivot that is not positive sets flag[0] = 1. */
+int tatrg_test_cholesky_blocked_inv(double* A, double* Dinv, double* Linv, double* T, int n,
+                                    int batch, int* flag, void* stream);
+
 /* Upper Cholesky factor R (G = R^T R) and its inverse of one n x n Gram (n <= 96), the
  * building block of the CholeskyQR orthonormalisation.  pass 0 factors
  * G + shift_coef * tr(G) * I and fails only on a non-positive or non-finite pivot; pass 1

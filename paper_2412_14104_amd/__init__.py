@@ -80,6 +80,8 @@ _SIGS = {
     "tatrg_test_tsqr": (ctypes.c_int, [_p, _i64, ctypes.c_int, _i64, _p, _p, _p]),
     "tatrg_test_svd": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int, ctypes.c_int, _p]),
     "tatrg_test_cholesky": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, _dbl, _p, _p]),
+    "tatrg_test_cholesky_blocked_inv": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int,
+                                                       ctypes.c_int, _p, _p]),
     "tatrg_test_chol_inv": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _p,
                                             _p]),
     "tatrg_test_philox": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),

@@ -73,6 +73,25 @@ void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fa
 void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int n, int batch,
                         int64_t sX, int64_t sL, hipStream_t st);
 
+// Right-looking blocked Cholesky of `batch` SPD n x n matrices (stride n*n) in place: A <- L
+// (lower, zeros above), with the inverses of its 64 x 64 diagonal blocks written to Dinv
+// (batch x ceil(n / 64) blocks of 64 x 64).  Per block column: the diagonal block and its
+// inverse (one wave), the panel below by a GEMM with that inverse, the trailing update by a
+// GEMM.  A non-positive pivot raises flag[0].
+void cholesky_blocked_inv(double* A, double* Dinv, int n, int batch, int* flag,
+                          hipStream_t st);
+
+// cholesky_blocked_inv of A + shift_rel * trace(A) * I (per matrix).
+void cholesky_shifted_inv(double* A, double* Dinv, int n, int batch, double shift_rel,
+                          int* flag, hipStream_t st);
+
+// Inverse of `batch` lower-triangular n x n matrices L (stride n*n) whose 64 x 64 diagonal
+// blocks are already inverted in Dinv (as cholesky_blocked_inv leaves them), by doubling the
+// inverted blocks: the off-diagonal block of [[A, 0], [B, C]]^{-1} is -C^{-1} B A^{-1}.
+// Linv: batch x n x n; T: scratch of at least n * n / 2 doubles.
+void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T, int n,
+                   int batch, hipStream_t st);
+
 // Checks the diagonal of `batch` lower Cholesky factors (n x n, stride n*n): *flag = 1 when a
 // diagonal entry is not finite or not positive, when the smallest pivot L_ii^2 is below
 // min_ratio times the largest, or when a pivot leaves (lo, hi).  Leaves *flag alone

@@ -172,7 +172,8 @@ struct tatrg_handle {
   // (cp, stride n5), their orthonormal factors (cq), the Cholesky factors of the two passes
   // (cg, cg2), T = L1 L2 = R^T (ct) and R_A (cra); cflag (device) and hflag (pinned host)
   // carry the conditioning verdict
-  double *cp, *cq, *cg, *cg2, *ctt, *ct, *cra;
+  double *cp, *cq, *cg, *cg2, *ctt, *ct, *cra, *cdi, *cli1, *cli2, *ctmp;
+  double* sqdi;  // inverses of the diagonal blocks of the six squeezer Cholesky factors
   int* cflag = nullptr;
   int* hflag = nullptr;
   size_t planes_doubles;
@@ -307,6 +308,10 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->cq = cv.take(2 * n5);
   h->cg = cv.take(2 * n2 * n2); h->cg2 = cv.take(2 * n2 * n2); h->ct = cv.take(2 * n2 * n2);
   h->ctt = cv.take(2 * n2 * n2);
+  h->cdi = cv.take(2 * (size_t)((n2 + 63) / 64) * 64 * 64);
+  h->cli1 = cv.take(2 * n2 * n2); h->cli2 = cv.take(2 * n2 * n2);
+  h->ctmp = cv.take(n2 * n2);
+  h->sqdi = cv.take(6 * (size_t)((n2 + 63) / 64) * 64 * 64);
   h->cra = cv.take(n2 * n2);
   h->cflag = (int*)cv.take(8);
   h->P1 = cv.take(n4 * Ls); h->P2 = cv.take(n4 * Ls);
@@ -642,29 +647,32 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
 
 // Orthonormal factors of the two swap panels, the canonical isometries reshaped as
 // P_A[f', (x g)] = A'[x, f', g] and P_B[b', (x g)] = B'[x, b', g] (chi^3 x chi^2 each, stored
-// in cp with stride n5, batched): CholeskyQR2 (two passes of Gram, Cholesky and triangular
-// solve), P = Q R^ with R^ = L2^T L1^T.  The cell middle's panels are P (1 x S'), with the
+// in cp with stride n5, batched): CholeskyQR2, P = Q R^ with Q = Q1 L2^{-T}, Q1 = P L1^{-T}
+// (L1, L2 the Cholesky factors of P^T P and Q1^T Q1) and R^ = L2^T L1^T.  Q1 is formed (cq)
+// because the second Gram must be taken of it; Q itself is only ever applied, as
+// Q1 L2^{-T}, so L2^{-1} is kept (cli2).  The cell middle's panels are P (1 x S'), with the
 // gauge-rotated weights S' of the canonical form on the g index, so its factors are
 // R = R^ (1 x S'); the isometries are far better conditioned than the weighted panels, whose
-// condition grows like 1 / s_min.  Writes Q to cq, R_A = (L1 L2)^T (1 x S') to cra and
-// R_B^T = (1 x S') L1 L2 to ct + chi^4.  cflag is raised when a pivot of the first pass is
-// below 1e-15 of the largest (condition beyond ~3e7, where two passes no longer give an
-// orthonormal Q to rounding; also every rank-deficient panel, as in the first steps or at
-// beta = 0) or a pivot of the second pass leaves (0.5, 2).
+// condition grows like 1 / s_min.  Writes R_A to cra and R_B^T = (1 x S') L1 L2 to
+// ct + chi^4.  cflag is raised when a pivot of the first pass is below 1e-15 of the largest
+// (condition beyond ~3e7, where two passes no longer give an orthonormal Q to rounding; also
+// every rank-deficient panel, as in the first steps or at beta = 0) or a pivot of the second
+// pass leaves (0.5, 2).
 void compress_swap_panels(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
   zero((double*)h->cflag, 1, st);
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
-  cholesky_shifted(h->cg, (int)n2, 2, 0.0, h->cflag, st);
+  cholesky_blocked_inv(h->cg, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st);
-  copy(h->cq, h->cp, 2 * n5, st);
-  trsm_right_lower_t(h->cq, n2, n3, h->cg, (int)n2, 2, n5, s2, st);
+  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  // Q1 = P L1^{-T}
+  gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
-  cholesky_shifted(h->cg2, (int)n2, 2, 0.0, h->cflag, st);
+  cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st);
-  trsm_right_lower_t(h->cq, n2, n3, h->cg2, (int)n2, 2, n5, s2, st);
+  tri_inv_lower(h->cg2, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st);
   // ctt = L1 L2 = R^^T, rows (x g); ct[(x b)] = sum_g S'[b, g] ctt[(x g)] (S' is symmetric)
   gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ctt, n2), 2, s2, s2, s2));
   gemm(h, Gb(G(c, n2, c, h->Smat, c, false, h->ctt, n2, false, h->ct, n2), 2 * c, 0, c * n2,
@@ -717,24 +725,29 @@ bool bond_swap(tatrg_handle* h, double* rec) {
   SwapOp op;
   op.h = h;
   if (compressed) {
-    const double* QA = h->cq;
-    const double* QB = h->cq + d.n5;
-    // the sketch of M, rows (beta, b') stored in (b', beta) order, then (Q_B x 1)^T Omega:
-    // rows (p', beta)
+    const double* Q1A = h->cq;
+    const double* Q1B = h->cq + d.n5;
+    const double* L2iA = h->cli2;
+    const double* L2iB = h->cli2 + d.n2 * d.n2;
+    // the sketch of M, rows (beta, b') stored in (b', beta) order, then
+    // (Q_B x 1)^T Omega = L2B^{-1} Q1B^T Omega: rows (p', beta)
     philox_gaussian(h->P2, d.n4, w, w, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
                     d.n3);
-    gemm_long_k(h, G(d.n2, c * w, d.n3, QB, d.n2, true, h->P2, c * w, false, h->P1, c * w));
+    gemm_long_k(h, G(d.n2, c * w, d.n3, Q1B, d.n2, true, h->P2, c * w, false, h->t1, c * w));
+    gemm(h, G(d.n2, c * w, d.n2, L2iB, d.n2, false, h->t1, c * w, false, h->P1, c * w));
     op.fa = h->cra;               // R_A
     op.na = d.n2;
     op.fb = h->ct + d.n2 * d.n2;  // R_B^T
     op.nb = d.n2;
     rsvd(h, op, d.n3, d.n3, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true, true);
-    // U~ = Q Uh[:, :c] as [p][(alpha g)]; X rows (f', alpha) = Q_A U~
+    // U~ = Q Uh[:, :c] as [p][(alpha g)]; X rows (f', alpha) = Q_A U~ = Q1A (L2A^{-T} U~)
     gemm(h, G(d.n3, c, w, h->P2, w, false, h->Uh, w, false, h->t1, c));
-    gemm(h, G(d.n3, d.n2, d.n2, QA, d.n2, false, h->t1, d.n2, false, h->Xs, d.n2));
+    gemm(h, G(d.n2, d.n2, d.n2, L2iA, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
+    gemm(h, G(d.n3, d.n2, d.n2, Q1A, d.n2, false, h->t2, d.n2, false, h->Xs, d.n2));
     perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
     gemm(h, G(d.n3, c, w, h->P1, w, false, h->Vh, w, false, h->t1, c));
-    gemm(h, G(d.n3, d.n2, d.n2, QB, d.n2, false, h->t1, d.n2, false, h->Xs, d.n2));
+    gemm(h, G(d.n2, d.n2, d.n2, L2iB, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
+    gemm(h, G(d.n3, d.n2, d.n2, Q1B, d.n2, false, h->t2, d.n2, false, h->Xs, d.n2));
     perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
   } else {
     // A~ = A' S', B~ = B' S'; atf = [f', (x beta)], btx = [(x alpha), b']
@@ -925,7 +938,7 @@ void squeezers(tatrg_handle* h, double* rec) {
   }
   symmetrize(h->rho, (int)n2, 6, st);
   copy(h->chol, h->rho, 6 * n2 * n2, st);
-  cholesky_shifted(h->chol, (int)n2, 6, CHOL_SHIFT, h->flag, st);
+  cholesky_shifted_inv(h->chol, h->sqdi, (int)n2, 6, CHOL_SHIFT, h->flag, st);
   const uint32_t sq_sites[3] = {SITE_SQZ_2, SITE_SQZ_3, SITE_SQZ_4};
   const uint32_t pr_sites[3] = {SITE_PROBE_SQZ_2, SITE_PROBE_SQZ_3, SITE_PROBE_SQZ_4};
   // the three squeezer pairs are independent after the Cholesky factors: one lane each

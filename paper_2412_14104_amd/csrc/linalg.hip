@@ -801,6 +801,168 @@ __global__ __launch_bounds__(256) void chol_check_kernel(const double* Lall, int
   if (threadIdx.x == 0 && (bad[0] || !(mn[0] >= min_ratio * mx[0]))) flag[0] = 1;
 }
 
+// Factor the (already updated) diagonal block at (j, j), jb <= 64, of every matrix of the
+// batch (one wave each) and write L_jj back (zero above its diagonal) and L_jj^{-1} to
+// Dinv[b][j / 64] (64 x 64, lower, zero-padded beyond jb).  The block is staged through LDS
+// with coalesced loads; lane r then holds row r.  The factorisation is the right-looking
+// column algorithm (pivot from lane k, column k published through LDS); the inverse is one
+// forward substitution per lane, lane c building column c.  A pivot that is not positive
+// raises flag[0].
+__global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double* Dinv, int n,
+                                                           int j, int jb, int* flag) {
+  __shared__ double blk[64][65];
+  __shared__ double lk[64];
+  double* A = Aall + (int64_t)blockIdx.y * n * n;
+  double* Di = Dinv + ((int64_t)blockIdx.y * ((n + 63) / 64) + j / 64) * 64 * 64;
+  const int r = threadIdx.x;
+  for (int rr = 0; rr < jb; ++rr)
+    blk[rr][r] = (r < jb) ? A[(int64_t)(j + rr) * n + j + r] : 0.0;
+  __syncthreads();
+  double row[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) row[c] = (r < jb && c < jb) ? blk[r][c] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < jb) {
+      const double piv = __shfl(row[k], k, 64);
+      if (r == 0 && !(piv > 0.0)) flag[0] = 1;
+      const double dk = (piv > 0.0) ? sqrt(piv) : __builtin_nan("");
+      if (r == k) row[k] = dk;
+      if (r > k) row[k] /= dk;
+      lk[r] = row[k];
+      __syncthreads();
+#pragma unroll
+      for (int c = k + 1; c < 64; ++c)
+        if (c <= r && r < jb) row[c] -= row[k] * lk[c];
+      __syncthreads();
+    }
+  }
+  // L_jj to LDS (lower, zero above) and back to A
+#pragma unroll
+  for (int c = 0; c < 64; ++c) blk[r][c] = (r < jb && c <= r) ? row[c] : 0.0;
+  __syncthreads();
+  for (int rr = 0; rr < jb; ++rr)
+    if (r < jb) A[(int64_t)(j + rr) * n + j + r] = blk[rr][r];
+  // column r of L_jj^{-1}: x_i = (delta_ir - sum_{r <= k < i} L_ik x_k) / L_ii, i >= r
+  double x[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    double v = 0.0;
+    if (i < jb && i >= r) {
+      v = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= blk[i][k] * x[k];
+      v /= blk[i][i];
+    }
+    x[i] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 64; ++i) blk[i][r] = x[i];
+  __syncthreads();
+  for (int rr = 0; rr < 64; ++rr) Di[rr * 64 + r] = blk[rr][r];
+}
+
+// Places the 64 x 64 diagonal-block inverses Dinv of `batch` lower matrices on the diagonal of
+// Linv (n x n, zero elsewhere).
+__global__ void place_diag_blocks_kernel(const double* Dinv, double* Linv, int n, int batch) {
+  const int nb = (n + 63) / 64;
+  const int64_t total = (int64_t)batch * n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / ((int64_t)n * n), rem = idx - b * n * n;
+    const int i = (int)(rem / n), c = (int)(rem - (rem / n) * n);
+    double v = 0.0;
+    if (i / 64 == c / 64) v = Dinv[((b * nb + i / 64) * 64 + (i % 64)) * 64 + (c % 64)];
+    Linv[idx] = v;
+  }
+}
+
+namespace {
+GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, bool ta,
+                   const double* B, int64_t ldb, bool tb, double* C, int64_t ldc, double alpha,
+                   double beta, int64_t batch, int64_t sA, int64_t sB, int64_t sC) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = sA; g.ta = ta;
+  g.B = B; g.ldb = ldb; g.sB = sB; g.tb = tb;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.alpha = alpha; g.beta = beta; g.batch = batch;
+  return g;
+}
+}  // namespace
+
+void cholesky_blocked_inv(double* A, double* Dinv, int n, int batch, int* flag,
+                          hipStream_t st) {
+  const int64_t s2 = (int64_t)n * n;
+  for (int j = 0; j < n; j += 64) {
+    const int jb = (n - j) < 64 ? (n - j) : 64;
+    hipLaunchKernelGGL(chol_diag_inv_kernel, dim3(1, batch), dim3(64), 0, st, A, Dinv, n, j, jb,
+                       flag);
+    const int rest = n - j - jb;
+    if (rest <= 0) break;
+    const int64_t nb = (n + 63) / 64;
+    // panel below the block, in place: L21 = A21 L_jj^{-T} (one column tile, so every
+    // work-group reads its rows before writing them)
+    double* A21 = A + (int64_t)(j + jb) * n + j;
+    gemm_f64(gemm_args(rest, jb, jb, A21, n, false, Dinv + (int64_t)(j / 64) * 64 * 64, 64, true,
+                       A21, n, 1.0, 0.0, batch, s2, nb * 64 * 64, s2), st);
+    // trailing update A22 -= L21 L21^T
+    double* A22 = A + (int64_t)(j + jb) * n + j + jb;
+    gemm_f64(gemm_args(rest, rest, jb, A21, n, false, A21, n, true, A22, n, -1.0, 1.0, batch, s2,
+                       s2, s2), st);
+  }
+  const int64_t total = s2 * batch;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, n, batch);
+}
+
+void cholesky_shifted_inv(double* A, double* Dinv, int n, int batch, double shift_rel,
+                          int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(add_shift_kernel, dim3(batch), dim3(1024), 0, st, A, n, shift_rel);
+  cholesky_blocked_inv(A, Dinv, n, batch, flag, st);
+}
+
+void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T, int n,
+                   int batch, hipStream_t st) {
+  const int64_t s2 = (int64_t)n * n;
+  {
+    const int64_t total = s2 * batch;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(place_diag_blocks_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Dinv,
+                       Linv, n, batch);
+  }
+  // doubling: for a pair of diagonal blocks [[A, 0], [B, C]] whose inverses are in place,
+  // the off-diagonal block of the inverse is -C^{-1} (B A^{-1})
+  for (int s = 64; s < n; s *= 2) {
+    const int pairs_full = n / (2 * s);
+    const int64_t stride = 2 * (int64_t)s * (n + 1);
+    for (int b = 0; b < batch; ++b) {
+      const double* Lb = L + b * s2;
+      double* Xb = Linv + b * s2;
+      if (pairs_full > 0) {
+        // T_i = B_i A_i^{-1}, X21_i = -C_i^{-1} T_i, for the pairs at o = 2 s i
+        gemm_f64(gemm_args(s, s, s, Lb + (int64_t)s * n, n, false, Xb, n, false, T, s, 1.0, 0.0,
+                           pairs_full, stride, stride, (int64_t)s * s), st);
+        gemm_f64(gemm_args(s, s, s, Xb + (int64_t)s * n + s, n, false, T, s, false,
+                           Xb + (int64_t)s * n, n, -1.0, 0.0, pairs_full, stride,
+                           (int64_t)s * s, stride), st);
+      }
+      const int o = pairs_full * 2 * s;
+      const int sc = n - o - s;  // a last, partial pair: A of size s, C of size sc < s
+      if (sc > 0) {
+        gemm_f64(gemm_args(sc, s, s, Lb + (int64_t)(o + s) * n + o, n, false,
+                           Xb + (int64_t)o * n + o, n, false, T, s, 1.0, 0.0, 1, 0, 0, 0), st);
+        gemm_f64(gemm_args(sc, s, sc, Xb + (int64_t)(o + s) * n + o + s, n, false, T, s, false,
+                           Xb + (int64_t)(o + s) * n + o, n, -1.0, 0.0, 1, 0, 0, 0), st);
+      }
+    }
+  }
+}
+
 void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int n, int batch,
                         int64_t sX, int64_t sL, hipStream_t st) {
   const int nbk = 64;

@@ -87,6 +87,14 @@ int tatrg_test_cholesky(double* A, int n, int batch, double shift_rel, int* flag
   return launched();
 }
 
+int tatrg_test_cholesky_blocked_inv(double* A, double* Dinv, double* Linv, double* T, int n,
+                                    int batch, int* flag, void* stream) {
+  if (!A || !Dinv || !Linv || !T || !flag || n < 1 || batch < 1) return -1;
+  cholesky_blocked_inv(A, Dinv, n, batch, flag, (hipStream_t)stream);
+  tri_inv_lower(A, Dinv, Linv, T, n, batch, (hipStream_t)stream);
+  return launched();
+}
+
 int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pass,
                         double shift_coef, int* fail, void* stream) {
   if (!G || !R || !Rinv || !fail || n < 1 || n > 96 || pass < 0 || pass > 2) return -1;

@@ -304,6 +304,49 @@ def test_cholesky_flags_indefinite_matrix(lib):
     assert host(flag)[0] == 1
 
 
+@pytest.mark.parametrize("n,batch", [(36, 1), (64, 2), (256, 2), (320, 1), (448, 1), (576, 2),
+                                     (1024, 2)])
+def test_cholesky_blocked_with_inverse(lib, n, batch):
+    """Right-looking blocked Cholesky (64-wide blocks, diagonal blocks inverted in one wave,
+    panels and trailing updates as GEMMs) and the triangular inverse by doubling the inverted
+    blocks, including sizes that leave a partial last block or an unpaired block at some
+    doubling level."""
+    rng = np.random.default_rng(7 * n + batch)
+    g = rng.standard_normal((batch, n, n + 5)) * np.logspace(0, -3, n + 5)[None, None, :]
+    a = g @ g.transpose(0, 2, 1)
+    da = dev(a)
+    nb = (n + 63) // 64
+    dinv = torch.empty(batch * nb * 64 * 64, dtype=torch.float64, device="cuda")
+    linv = torch.empty((batch, n, n), dtype=torch.float64, device="cuda")
+    tmp = torch.empty(n * n, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(4, dtype=torch.int32, device="cuda")
+    assert lib.tatrg_test_cholesky_blocked_inv(vp(da), vp(dinv), vp(linv), vp(tmp), n, batch,
+                                               vp(flag), stream()) == 0
+    low, inv = host(da), host(linv)
+    assert host(flag)[0] == 0
+    for i in range(batch):
+        assert np.abs(np.triu(low[i], 1)).max() == 0.0
+        assert np.abs(np.triu(inv[i], 1)).max() == 0.0
+        assert np.abs(low[i] @ low[i].T - a[i]).max() < 1e-13 * np.abs(a[i]).max()
+        # backward error of the inverse: |Linv L - I| <= c n u cond(L)
+        cond = np.linalg.cond(low[i])
+        assert np.abs(inv[i] @ low[i] - np.eye(n)).max() < 4 * n * 1.1e-16 * cond
+
+
+def test_cholesky_blocked_flags_indefinite_matrix(lib):
+    n = 100
+    a = np.eye(n)
+    a[70, 70] = -1.0
+    da = dev(a)
+    dinv = torch.empty(2 * 64 * 64, dtype=torch.float64, device="cuda")
+    linv = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    tmp = torch.empty(n * n, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(4, dtype=torch.int32, device="cuda")
+    assert lib.tatrg_test_cholesky_blocked_inv(vp(da), vp(dinv), vp(linv), vp(tmp), n, 1,
+                                               vp(flag), stream()) == 0
+    assert host(flag)[0] == 1
+
+
 @pytest.mark.parametrize("n,pass_", [(1, 1), (7, 0), (32, 1), (96, 0), (96, 1), (96, 2)])
 def test_chol_inv_factor_and_inverse(lib, n, pass_):
     rng = np.random.default_rng(100 * n + pass_)
