@@ -112,6 +112,15 @@ int tatrg_profile_enable(struct tatrg_handle* h, int max_launches);
 int tatrg_profile_read(struct tatrg_handle* h, double* total_ms, int32_t* launches,
                        double* flops_per_launch);
 
+/* Speculation on the CholeskyQR orthonormalisations of a step: after a step in which no
+ * CholeskyQR pass failed, the next step of that temperature does not launch the Householder
+ * fallback kernels; a failed pass is caught at the end of the step, whose input was saved,
+ * and the step is replayed with the fallback.  Speculation is otherwise limited to steps
+ * after one with no failed pass that took the compressed cell middle.  on = 1 makes every
+ * following step speculate, on = 0 restores the rule, on < 0 leaves it; *replays (may be
+ * NULL) receives the number of replays so far.  Returns 0, -1 for a null handle. */
+int tatrg_test_speculation(struct tatrg_handle* h, int on, int64_t* replays);
+
 /* Stage timing of the profiled steps (tatrg_profile_enable also reserves events at the stage
  * boundaries of up to ceil(max_launches / 4) steps, on the handle's stream, which the lanes
  * rejoin before each boundary).  Synchronises; stage_ms[0..5] (host) receives the summed

@@ -62,10 +62,10 @@ void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hi
 // pass 0 factors G + shift_coef * tr(G) * I (the shifted first pass of CholeskyQR3) and fails
 // only on a non-finite or non-positive pivot; pass 1 fails when a pivot is <= 1e-14 of the
 // largest diagonal entry; pass 2 (G close to the identity) when a pivot leaves (0.25, 4).  A
-// failure sets *fail = pass + 1 and leaves R, Rinv unwritten.  Does nothing when *fail is
-// already set.
+// failure sets *fail = pass + 1 (and, when sticky is given, ORs 1 into *sticky) and leaves
+// R, Rinv unwritten.  Does nothing when *fail is already set.
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
-              hipStream_t st, double shift_coef = 0.0);
+              hipStream_t st, double shift_coef = 0.0, int* sticky = nullptr);
 
 // Solves X L^T = B in place for `batch` tall panels X (m x n, leading dim ldx, stride sX)
 // with lower-triangular L (n x n, stride sL): column blocks of 64, each a GEMM update by the
@@ -77,7 +77,7 @@ void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int 
 // (lower, zeros above), with the inverses of its 64 x 64 diagonal blocks written to Dinv
 // (batch x ceil(n / 64) blocks of 64 x 64).  Per block column: the diagonal block and its
 // inverse (one wave), the panel below by a GEMM with that inverse, the trailing update by a
-// GEMM.  A non-positive pivot raises flag[0].
+// GEMM.  A non-positive pivot ORs 1 into flag[0].
 void cholesky_blocked_inv(double* A, double* Dinv, int n, int batch, int* flag,
                           hipStream_t st);
 
@@ -92,12 +92,12 @@ void cholesky_shifted_inv(double* A, double* Dinv, int n, int batch, double shif
 void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T, int n,
                    int batch, hipStream_t st);
 
-// Checks the diagonal of `batch` lower Cholesky factors (n x n, stride n*n): *flag = 1 when a
-// diagonal entry is not finite or not positive, when the smallest pivot L_ii^2 is below
-// min_ratio times the largest, or when a pivot leaves (lo, hi).  Leaves *flag alone
+// Checks the diagonal of `batch` lower Cholesky factors (n x n, stride n*n): ORs `code` into
+// *flag when a diagonal entry is not finite or not positive, when the smallest pivot L_ii^2
+// is below min_ratio times the largest, or when a pivot leaves (lo, hi).  Leaves *flag alone
 // otherwise.
 void chol_check(const double* L, int n, int batch, double min_ratio, double lo, double hi,
-                int* flag, hipStream_t st);
+                int* flag, hipStream_t st, int code = 1);
 
 // ---------------------------------------------------------------------------- small dense
 // One-sided Jacobi SVD of `batch` square n x n matrices (n <= 96): A = U diag(S) V^T with S

@@ -95,6 +95,10 @@ __global__ void mask_kernel(const double* S, double* D, int n, double cutoff) {
   D[i] = (S[i] > cutoff * smax) ? 1.0 / sqrt(S[i]) : 0.0;
 }
 
+__global__ void zero_int_kernel(int* x) {
+  if (threadIdx.x == 0) x[0] = 0;
+}
+
 __global__ void copy_small_kernel(double* dst, const double* src, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
@@ -161,6 +165,8 @@ struct tatrg_handle {
   int step = 0;
   bool initialized = false;
   bool host_fault = false;  // a stage could not be enqueued (reported by tatrg_step)
+  int64_t replays = 0;      // steps replayed after a speculation on the CholeskyQR passes failed
+  bool force_speculation = false;  // testing: speculate on every step
   std::vector<double> betas;
   // buffers
   double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
@@ -170,12 +176,29 @@ struct tatrg_handle {
   double *partial, *probe, *small, *planes;
   // compressed cell middle of the bond swap: the two panels [f'][(x beta)], [b'][(x alpha)]
   // (cp, stride n5), their orthonormal factors (cq), the Cholesky factors of the two passes
-  // (cg, cg2), T = L1 L2 = R^T (ct) and R_A (cra); cflag (device) and hflag (pinned host)
-  // carry the conditioning verdict
-  double *cp, *cq, *cg, *cg2, *ctt, *ct, *cra, *cdi, *cli1, *cli2, *ctmp;
+  // (cg, cg2), T = L1 L2 = R^T (ct) and R_A (cra); cflag carries the conditioning verdict
+  double *cp, *cq, *cg, *cg2, *ctt, *ct, *cra, *cdi, *cli1, *cli2, *ctmp, *cg3;
+  double* cqx = nullptr;  // the explicit orthonormal-up-to-the-last-pass panels (cq or cp)
   double* sqdi;  // inverses of the diagonal blocks of the six squeezer Cholesky factors
   int* cflag = nullptr;
-  int* hflag = nullptr;
+  int* vflags = nullptr;  // device: [0] compression verdict, [2 + slot] CholeskyQR verdicts
+  // Householder fallback of the CholeskyQR orthonormalisations: while `speculate` is set the
+  // fallback kernels are not launched; every failed CholeskyQR pass ORs into orth_sticky, which
+  // the end of the step reads, replaying the step with the fallback from the saved state
+  // (save_phi, save_psi, save_small) when a pass did fail
+  bool speculate = false;
+  int* orth_sticky = nullptr;
+  // the inputs of the last two temperature-steps (alternating slots): phi, psi, and acc with
+  // the fault flag
+  double *save_phi[2] = {nullptr, nullptr}, *save_psi[2] = {nullptr, nullptr};
+  double *save_small[2] = {nullptr, nullptr};
+  int64_t seq = 0;  // temperature-steps enqueued (selects the save slot)
+  // the last temperature-step: its CholeskyQR verdict (vflags[2 + slot]) is read at the next
+  // synchronisation point; when it ran speculatively and a pass failed it is replayed
+  struct Pending {
+    bool active = false, spec = false;
+    int b = 0, k = 0, slot = 0;
+  } pending;
   size_t planes_doubles;
   int* flag;
   double* acc;
@@ -221,6 +244,7 @@ struct tatrg_handle {
     double *spectra = nullptr, *xrec = nullptr, *ttr = nullptr;
     int* flag = nullptr;
     std::vector<signed char> swap_compressed;  // per step: 1 compressed middle, 0 full, -1 not run
+    bool need_fallback = true;  // a CholeskyQR pass failed in this temperature's last step
   };
   std::vector<State> states;
   hipEvent_t fork = nullptr;
@@ -230,6 +254,8 @@ struct tatrg_handle {
 namespace {
 
 constexpr int MAX_BATCH = 1024;
+
+void zero_int(int* x, hipStream_t st) { hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, st, x); }
 
 void select_state(tatrg_handle* h, int b) {
   const tatrg_handle::State& s = h->states[b];
@@ -311,9 +337,16 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->cdi = cv.take(2 * (size_t)((n2 + 63) / 64) * 64 * 64);
   h->cli1 = cv.take(2 * n2 * n2); h->cli2 = cv.take(2 * n2 * n2);
   h->ctmp = cv.take(n2 * n2);
+  h->cg3 = cv.take(2 * n2 * n2);
   h->sqdi = cv.take(6 * (size_t)((n2 + 63) / 64) * 64 * 64);
   h->cra = cv.take(n2 * n2);
-  h->cflag = (int*)cv.take(8);
+  h->vflags = (int*)cv.take(8);
+  h->cflag = h->vflags;            // vflags[0]: compression verdict
+  h->orth_sticky = h->vflags + 2;  // vflags[2 + slot]: CholeskyQR verdict of a step
+  for (int sl = 0; sl < 2; ++sl) {
+    h->save_phi[sl] = cv.take(n5); h->save_psi[sl] = cv.take(n5);
+    h->save_small[sl] = cv.take(8);
+  }
   h->P1 = cv.take(n4 * Ls); h->P2 = cv.take(n4 * Ls);
   h->P3 = cv.take(n4 * std::max(Ls, c));
   h->Gq = cv.take(6 * (int64_t)MAX_W * MAX_W);
@@ -504,22 +537,26 @@ void orth(tatrg_handle* h, double* Y, int64_t m, int n, int64_t ld, double* R_ou
     g.cond_when = false;
     return g;
   };
+  int* sticky = h->speculate ? h->orth_sticky : nullptr;
   // pass 0 (shifted)
   gemm_long_k(h, G(n, n, m, Y, ld, true, Y, ld, false, G1, n));
-  chol_inv(G1, R0, Ri, n, 0, fail, st, shift);
+  chol_inv(G1, R0, Ri, n, 0, fail, st, shift, sticky);
   gemm(h, when_ok(G(m, n, n, Y, ld, false, Ri, n, false, h->P3, n)));
   // pass 1
   gemm_long_k(h, when_ok(G(n, n, m, h->P3, n, true, h->P3, n, false, G1, n)));
-  chol_inv(G1, R1, Ri, n, 1, fail, st);
+  chol_inv(G1, R1, Ri, n, 1, fail, st, 0.0, sticky);
   gemm(h, when_ok(G(m, n, n, h->P3, n, false, Ri, n, false, Y, ld)));
   // pass 2, in place
   gemm_long_k(h, when_ok(G(n, n, m, Y, ld, true, Y, ld, false, G1, n)));
-  chol_inv(G1, R2, Ri, n, 2, fail, st);
+  chol_inv(G1, R2, Ri, n, 2, fail, st, 0.0, sticky);
   gemm(h, when_ok(G(m, n, n, Y, ld, false, Ri, n, false, Y, ld)));
   if (R_out) {  // success: R = R2 R1 R0
     gemm(h, when_ok(G(n, n, n, R2, n, false, R1, n, false, Rt, n)));
     gemm(h, when_ok(G(n, n, n, Rt, n, false, R0, n, false, R_out, n)));
   }
+  // speculating that no pass fails: the fallback is not launched (a failure is caught at the
+  // end of the step through the sticky flag, and the step is replayed)
+  if (h->speculate) return;
   // failure in pass 1 or 2: factorise the pass-0 panel
   hipLaunchKernelGGL(copy_panel_when_kernel, dim3(grid_for(m * n)), dim3(TPB), 0, st, h->P3,
                      (int64_t)n, Y, ld, m, n, fail, 2, 3);
@@ -658,46 +695,71 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
 // (condition beyond ~3e7, where two passes no longer give an orthonormal Q to rounding; also
 // every rank-deficient panel, as in the first steps or at beta = 0) or a pivot of the second
 // pass leaves (0.5, 2).
+void weights_into_r(tatrg_handle* h);
+
 void compress_swap_panels(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
   zero((double*)h->cflag, 1, st);
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
+  // a zero column of a panel (a zero diagonal entry of its Gram) is structural rank deficiency
+  chol_check(h->cg, (int)n2, 2, 0.0, 0.0, INFINITY, h->cflag, st, 8);
   cholesky_blocked_inv(h->cg, h->cdi, (int)n2, 2, h->cflag, st);
-  chol_check(h->cg, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st);
+  chol_check(h->cg, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st, 2);
   tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
   // Q1 = P L1^{-T}
   gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
-  chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st);
+  chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st, 4);
   tri_inv_lower(h->cg2, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st);
+  h->cqx = h->cq;
   // ctt = L1 L2 = R^^T, rows (x g); ct[(x b)] = sum_g S'[b, g] ctt[(x g)] (S' is symmetric)
   gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ctt, n2), 2, s2, s2, s2));
-  gemm(h, Gb(G(c, n2, c, h->Smat, c, false, h->ctt, n2, false, h->ct, n2), 2 * c, 0, c * n2,
-             c * n2));
-  transpose_batched(h->ct, h->cra, (int)n2, (int)n2, 1, st);
+  weights_into_r(h);
 }
 
-// Whether the compressed middle may be used: one host round trip for the device verdict.
-bool compression_ok(tatrg_handle* h) {
-  int v = 1;
-  if (h->hflag) {
-    if (hipMemcpyAsync(h->hflag, h->cflag, sizeof(int), hipMemcpyDeviceToHost, h->st) !=
-            hipSuccess ||
-        hipStreamSynchronize(h->st) != hipSuccess) {
-      h->host_fault = true;
-      h->err = "bond swap: reading the compression verdict failed";
-      return false;
-    }
-    v = *h->hflag;
-  } else if (hipMemcpy(&v, h->cflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
-    h->host_fault = true;
-    h->err = "bond swap: reading the compression verdict failed";
-    return false;
-  }
-  return v == 0;
+// ct[(x b)] = sum_g S'[b, g] ctt[(x g)] for both panels (S' is symmetric), and R_A = ct[0]^T.
+void weights_into_r(tatrg_handle* h) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2;
+  gemm(h, Gb(G(c, n2, c, h->Smat, c, false, h->ctt, n2, false, h->ct, n2), 2 * c, 0, c * n2,
+             c * n2));
+  transpose_batched(h->ct, h->cra, (int)n2, (int)n2, 1, h->st);
+}
+
+// Second attempt, for panels without a zero column that were too ill-conditioned for two
+// passes: shifted CholeskyQR3 (Fukaya,
+// Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020).  Pass 1 factors P^T P + s I with
+// s = 11 (m n + n (n + 1)) u tr(P^T P), which bounds the condition of Q1 = P L1^{-T}; passes
+// 2 and 3 are plain, Q2 = Q1 L2^{-T} is formed (in cp) and Q = Q2 L3^{-T} is applied
+// implicitly.  R^ = L3^T L2^T L1^T.  cflag as in the first attempt.
+void compress_swap_panels_shifted(tatrg_handle* h) {
+  const Dims& d = h->d;
+  hipStream_t st = h->st;
+  const int64_t n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
+  const double shift = 11.0 * ((double)n3 * n2 + (double)n2 * (n2 + 1)) * 1.1102230246251565e-16;
+  zero((double*)h->cflag, 1, st);
+  gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
+  cholesky_shifted_inv(h->cg, h->cdi, (int)n2, 2, shift, h->cflag, st);
+  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
+  gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
+  cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
+  chol_check(h->cg2, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st, 2);
+  tri_inv_lower(h->cg2, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  // Q2 = Q1 L2^{-T} into cp (the panels are no longer needed)
+  gemm(h, Gb(G(n3, n2, n2, h->cq, n2, false, h->cli1, n2, true, h->cp, n2), 2, n5, s2, n5));
+  gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg3, n2), 2, n5, n5, s2));
+  cholesky_blocked_inv(h->cg3, h->cdi, (int)n2, 2, h->cflag, st);
+  chol_check(h->cg3, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st, 4);
+  tri_inv_lower(h->cg3, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st);
+  h->cqx = h->cp;
+  // ctt = L1 L2 L3
+  gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ct, n2), 2, s2, s2, s2));
+  gemm(h, Gb(G(n2, n2, n2, h->ct, n2, false, h->cg3, n2, false, h->ctt, n2), 2, s2, s2, s2));
+  weights_into_r(h);
 }
 
 // Bond swap (Section 2, Eq. (1)): rank-chi randomized SVD of the cell middle M, which gives
@@ -706,27 +768,30 @@ bool compression_ok(tatrg_handle* h) {
 // Q_B orthonormal, the randomized SVD of M with the sketch Omega is the one of K with the
 // sketch (Q_B x 1)^T Omega, lifted back by Q_A and Q_B, and each product with K costs
 // 4 chi^5 Ls instead of 4 chi^6 Ls (Table 1 prices bond swapping at O(q r chi^6)).  When the
-// panels are too ill-conditioned for that (compress_swap_panels), or with swap_mode = 1, the
-// products run on the full middle instead; both give the same X, sigma, Y up to rounding.
-// Returns whether the compressed middle was used.
-bool bond_swap(tatrg_handle* h, double* rec) {
+// panels are too ill-conditioned for that (compress_swap_panels, verdict read by the caller),
+// or with swap_mode = 1, the products run on the full middle instead; both give the same X,
+// sigma, Y up to rounding.  Returns whether the compressed middle was used.
+// The compression of the swap panels (enqueued; its verdict is read at the step's
+// synchronisation point).
+void swap_prepare(tatrg_handle* h) {
+  const Dims& d = h->d;
+  const int c = d.c;
+  // P_A = [f', (x g)] and P_B = [b', (x g)] from A' and B'
+  perm(h, h->A, h->cp, {c, d.n3, c}, {1, 0, 2});
+  perm(h, h->B, h->cp + d.n5, {c, d.n3, c}, {1, 0, 2});
+  compress_swap_panels(h);
+}
+
+bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int c = d.c;
   const int w = d.Ls;
-  bool compressed = false;
-  if (h->cfg.swap_mode == 0) {
-    // P_A = [f', (x g)] and P_B = [b', (x g)] from A' and B'
-    perm(h, h->A, h->cp, {c, d.n3, c}, {1, 0, 2});
-    perm(h, h->B, h->cp + d.n5, {c, d.n3, c}, {1, 0, 2});
-    compress_swap_panels(h);
-    compressed = compression_ok(h);
-  }
   SwapOp op;
   op.h = h;
   if (compressed) {
-    const double* Q1A = h->cq;
-    const double* Q1B = h->cq + d.n5;
+    const double* Q1A = h->cqx;
+    const double* Q1B = h->cqx + d.n5;
     const double* L2iA = h->cli2;
     const double* L2iB = h->cli2 + d.n2 * d.n2;
     // the sketch of M, rows (beta, b') stored in (b', beta) order, then
@@ -1084,8 +1149,6 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
          hipEventCreateWithFlags(&h->lane[z].done, hipEventDisableTiming) == hipSuccess;
   }
   h->lanes = ok;
-  void* hp = nullptr;
-  if (hipHostMalloc(&hp, 64, hipHostMallocDefault) == hipSuccess) h->hflag = (int*)hp;
   (void)hipGetLastError();
   *out = h;
   return TATRG_OK;
@@ -1118,12 +1181,183 @@ tatrg_status tatrg_init_tensor(tatrg_handle* h, const double* h_betas) {
     zero(h->xrec, h->cfg.n_steps + 1, st);
     zero(h->ttr, 8, st);
   }
+  for (tatrg_handle::State& sta : h->states) sta.need_fallback = true;
+  h->pending.active = false;
   select_state(h, 0);
   h->step = 0;
   h->initialized = true;
   if (!hip_ok(h, "init_tensor")) return TATRG_EHIP;
   return TATRG_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Phase A of a temperature-step: the order parameter record, the canonical form and the
+// compression of the swap panels (up to the step's synchronisation point).
+void step_phase_a(tatrg_handle* h, int b, double* rec, bool timed) {
+  auto mark = [&](int i) {
+    if (timed) hipEventRecord(h->sev[h->sev_used + i], h->st);
+  };
+  if (rec)
+    order_parameter(h->phi, h->psi, h->d.c, open_slot(h->step), h->partial, h->xrec + h->step,
+                    h->st);
+  mark(0);
+  canonicalize(h, h->step, rec);
+  mark(1);
+  if (h->cfg.swap_mode == 0) swap_prepare(h);
+  (void)b;
+}
+
+// Phase B: bond swap, isometries, triad, squeezers, contraction and rotation.
+void step_phase_b(tatrg_handle* h, int b, double* rec, bool timed, bool compressed) {
+  auto mark = [&](int i) {
+    if (timed) hipEventRecord(h->sev[h->sev_used + i], h->st);
+  };
+  const bool comp = bond_swap(h, rec ? rec + h->d.c : nullptr, compressed);
+  if (h->step < (int)h->states[b].swap_compressed.size())
+    h->states[b].swap_compressed[h->step] = comp ? 1 : 0;
+  mark(2);
+  isometries(h);
+  mark(3);
+  triad(h);
+  mark(4);
+  squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
+  mark(5);
+  contraction(h);
+  mark(6);
+  if (timed) h->sev_used += tatrg_handle::STAGE_EVENTS;
+}
+
+// The step's synchronisation point: waits for the stream and reads the compression verdict
+// (vflags[0]) and, when one is pending, the previous temperature-step's CholeskyQR verdict
+// (vflags[2 + slot]).  Returns false on a HIP error.
+bool sync_point(tatrg_handle* h, bool want_compression, bool* compressed, bool* prev_failed,
+                int* verdict = nullptr) {
+  *compressed = false;
+  *prev_failed = false;
+  // wait for the stream, then read the verdicts (one small copy from an idle device)
+  if (hipStreamSynchronize(h->st) != hipSuccess) return false;
+  int v[4] = {1, 0, 1, 1};
+  if (hipMemcpy(v, h->vflags, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return false;
+  *compressed = want_compression && v[0] == 0;
+  if (verdict) *verdict = v[0];
+  if (h->pending.active) {
+    // the last temperature-step's CholeskyQR verdict: whether its temperature still needs the
+    // fallback, and whether it has to be replayed (it ran without the fallback)
+    const bool failed = v[2 + h->pending.slot] != 0;
+    h->states[h->pending.b].need_fallback = failed;
+    *prev_failed = failed && h->pending.spec;
+    if (!*prev_failed) h->pending.active = false;
+  }
+  return true;
+}
+
+// Phase A, the synchronisation point and -- when the compression failed with every pivot
+// positive -- the shifted three-pass compression with a second synchronisation.  Returns
+// false on a HIP error.
+bool phase_a_and_sync(tatrg_handle* h, int b, double* rec, bool timed, bool* compressed,
+                      bool* prev_failed) {
+  step_phase_a(h, b, rec, timed);
+  *compressed = false;
+  *prev_failed = false;
+  int verdict = 0;
+  if (h->cfg.swap_mode == 0 || h->pending.active)
+    if (!sync_point(h, h->cfg.swap_mode == 0, compressed, prev_failed, &verdict)) return false;
+  if (!*prev_failed && h->cfg.swap_mode == 0 && !*compressed && !(verdict & 8)) {
+    // no zero column: ill-conditioned rather than structurally rank deficient, so the shifted
+    // three-pass factorisation may still compress the middle
+    compress_swap_panels_shifted(h);
+    bool dummy = false;
+    if (!sync_point(h, true, compressed, &dummy)) return false;
+  }
+  return true;
+}
+
+void restore_state(tatrg_handle* h, int b, int slot) {
+  select_state(h, b);
+  copy(h->phi, h->save_phi[slot], h->d.n5, h->st);
+  copy(h->psi, h->save_psi[slot], h->d.n5, h->st);
+  copy(h->acc, h->save_small[slot], 1, h->st);
+  copy((double*)h->flag, h->save_small[slot] + 1, 1, h->st);
+}
+
+// One temperature-step of state b at step index h->step.  Saves the input, enqueues phase A,
+// synchronises (verifying a pending speculative step and replaying it when its CholeskyQR
+// passes failed without the fallback), then phase B.  Speculating (when the last step of b
+// had no failed pass), the Householder fallbacks are not launched; the step is then left
+// pending until the next synchronisation point.
+bool temperature_step(tatrg_handle* h, int b) {
+  for (;;) {
+    select_state(h, b);
+    tatrg_handle::State& state = h->states[b];
+    const int slot = (int)(h->seq & 1);
+    copy(h->save_phi[slot], h->phi, h->d.n5, h->st);
+    copy(h->save_psi[slot], h->psi, h->d.n5, h->st);
+    copy(h->save_small[slot], h->acc, 1, h->st);
+    copy(h->save_small[slot] + 1, (const double*)h->flag, 1, h->st);
+    h->orth_sticky = h->vflags + 2 + slot;
+    zero_int(h->orth_sticky, h->st);
+    // speculate once this temperature's last step had no failed CholeskyQR pass and took the
+    // compressed cell middle (the panels of the full middle come with rank-deficient steps)
+    h->speculate = h->force_speculation ||
+                   (!state.need_fallback && h->step > 0 &&
+                    state.swap_compressed[h->step - 1] == 1);
+    const bool spec_a = h->speculate;
+    double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
+    const bool timed =
+        h->profile && h->sev_used + tatrg_handle::STAGE_EVENTS <= (int)h->sev.size();
+    bool compressed = false, prev_failed = false;
+    if (!phase_a_and_sync(h, b, rec, timed, &compressed, &prev_failed)) {
+      h->err = "step: synchronisation failed";
+      h->host_fault = true;
+      return false;
+    }
+    if (prev_failed) {
+      // the previous temperature-step ran without the fallback and a CholeskyQR pass failed:
+      // restore this step's input, replay that step with the fallback, then start over
+      const tatrg_handle::Pending p = h->pending;
+      h->pending.active = false;
+      h->replays += 1;
+      restore_state(h, b, slot);
+      const int save_step = h->step;
+      h->step = p.k;
+      h->states[p.b].need_fallback = true;
+      restore_state(h, p.b, p.slot);
+      h->speculate = false;
+      double* prec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c
+                                           : nullptr;
+      bool pcomp = false, dummy = false;
+      if (!phase_a_and_sync(h, p.b, prec, false, &pcomp, &dummy)) {
+        h->err = "step: synchronisation failed";
+        h->host_fault = true;
+        return false;
+      }
+      step_phase_b(h, p.b, prec, false, pcomp);
+      h->step = save_step;
+      continue;  // this temperature-step from its (restored) input
+    }
+    // a cell middle too ill-conditioned to compress goes with sketch panels that CholeskyQR may
+    // not orthonormalise: no speculation for the rest of this step
+    if (h->cfg.swap_mode == 0 && !compressed) h->speculate = false;
+    step_phase_b(h, b, rec, timed, compressed);
+    // the verdict of this step's CholeskyQR passes (vflags[2 + slot]) is read at the next
+    // synchronisation point
+    h->pending.active = true;
+    h->pending.spec = spec_a || h->speculate;
+    h->pending.b = b;
+    h->pending.k = h->step;
+    h->pending.slot = slot;
+    h->speculate = false;
+    h->seq += 1;
+    return true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
 
 tatrg_status tatrg_step(tatrg_handle* h) {
   if (!h) return TATRG_EINVAL;
@@ -1132,35 +1366,8 @@ tatrg_status tatrg_step(tatrg_handle* h) {
     return TATRG_ESTATE;
   }
   // the temperatures of the batch in turn, each through the whole step
-  for (int b = 0; b < h->cfg.batch; ++b) {
-    select_state(h, b);
-    double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
-    // stage timing (profiling only): events on the handle's stream, which every lane joins
-    // before the next stage starts
-    const bool timed = h->profile && h->sev_used + tatrg_handle::STAGE_EVENTS <= (int)h->sev.size();
-    auto mark = [&](int i) {
-      if (timed) hipEventRecord(h->sev[h->sev_used + i], h->st);
-    };
-    if (rec)
-      order_parameter(h->phi, h->psi, h->d.c, open_slot(h->step), h->partial,
-                      h->xrec + h->step, h->st);
-    mark(0);
-    canonicalize(h, h->step, rec);
-    mark(1);
-    const bool comp = bond_swap(h, rec ? rec + h->d.c : nullptr);
-    if (h->step < (int)h->states[b].swap_compressed.size())
-      h->states[b].swap_compressed[h->step] = comp ? 1 : 0;
-    mark(2);
-    isometries(h);
-    mark(3);
-    triad(h);
-    mark(4);
-    squeezers(h, rec ? rec + 2 * h->d.c : nullptr);
-    mark(5);
-    contraction(h);
-    mark(6);
-    if (timed) h->sev_used += tatrg_handle::STAGE_EVENTS;
-  }
+  for (int b = 0; b < h->cfg.batch; ++b)
+    if (!temperature_step(h, b)) break;
   select_state(h, 0);
   if (!hip_ok(h, "step")) return TATRG_EHIP;
   if (h->host_fault) return TATRG_EHIP;
@@ -1297,7 +1504,37 @@ tatrg_status tatrg_rsvd_noalloc(const double* d_A, int64_t m, int64_t n, int64_t
   return standalone_rsvd(&h, d_A, m, n, lda, k, w, q, seed, site, d_U, d_S, d_Vt);
 }
 
+namespace {
+// Verifies the last temperature-step when it ran speculatively, replaying it with the
+// Householder fallback when one of its CholeskyQR passes failed (see temperature_step).
+bool settle(tatrg_handle* h) {
+  if (!h->pending.active) return true;
+  bool comp = false, failed = false;
+  if (!sync_point(h, false, &comp, &failed)) return false;
+  if (!failed) return true;
+  const tatrg_handle::Pending p = h->pending;
+  h->pending.active = false;
+  h->replays += 1;
+  const int save_step = h->step;
+  h->step = p.k;
+  h->states[p.b].need_fallback = true;
+  restore_state(h, p.b, p.slot);
+  h->speculate = false;
+  double* rec = h->cfg.record_spectra ? h->spectra + (int64_t)h->step * 5 * h->d.c : nullptr;
+  bool pcomp = false, dummy = false;
+  if (!phase_a_and_sync(h, p.b, rec, false, &pcomp, &dummy)) return false;
+  step_phase_b(h, p.b, rec, false, pcomp);
+  h->step = save_step;
+  select_state(h, 0);
+  return hipStreamSynchronize(h->st) == hipSuccess;
+}
+}  // namespace
+
 static tatrg_status sync_check(tatrg_handle* h) {
+  if (!settle(h)) {
+    h->err = "verification of the last step failed";
+    return TATRG_EHIP;
+  }
   if (hipStreamSynchronize(h->st) != hipSuccess) {
     h->err = "stream synchronisation failed";
     return TATRG_EHIP;
@@ -1333,6 +1570,10 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
   if (!h->initialized || h->step != h->cfg.n_steps) {
     h->err = "free_energy needs exactly n_steps completed steps";
     return TATRG_ESTATE;
+  }
+  if (!settle(h)) {
+    h->err = "verification of the last step failed";
+    return TATRG_EHIP;
   }
   const Dims& d = h->d;
   const int nparts = 1024;
@@ -1422,6 +1663,10 @@ tatrg_status tatrg_get_state(tatrg_handle* h, double* d_phi, double* d_psi, int3
     h->err = "get_state / set_state need batch = 1";
     return TATRG_EINVAL;
   }
+  if (!settle(h)) {
+    h->err = "verification of the last step failed";
+    return TATRG_EHIP;
+  }
   copy(d_phi, h->phi, h->d.n5, h->st);
   copy(d_psi, h->psi, h->d.n5, h->st);
   if (step) *step = h->step;
@@ -1447,6 +1692,8 @@ tatrg_status tatrg_set_state(tatrg_handle* h, const double* d_phi, const double*
   copy(h->phi, d_phi, h->d.n5, h->st);
   copy(h->psi, d_psi, h->d.n5, h->st);
   zero((double*)h->flag, 4, h->st);
+  h->states[0].need_fallback = true;
+  h->pending.active = false;
   if (hipStreamSynchronize(h->st) != hipSuccess) return TATRG_EHIP;
   hipMemcpy(h->acc, &acc, sizeof(double), hipMemcpyHostToDevice);
   h->step = step;
@@ -1499,6 +1746,13 @@ int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
   return 0;
 }
 
+int tatrg_test_speculation(tatrg_handle* h, int on, int64_t* replays) {
+  if (!h) return -1;
+  if (on >= 0) h->force_speculation = on != 0;
+  if (replays) *replays = h->replays;
+  return 0;
+}
+
 int tatrg_profile_read_stages(tatrg_handle* h, double* stage_ms, int32_t* steps) {
   if (!h || !stage_ms || !steps) return -1;
   if (hipStreamSynchronize(h->st) != hipSuccess) return -3;
@@ -1528,7 +1782,6 @@ void tatrg_destroy(tatrg_handle* h) {
     if (h->lane[z].done) hipEventDestroy(h->lane[z].done);
   }
   if (h->fork) hipEventDestroy(h->fork);
-  if (h->hflag) hipHostFree(h->hflag);
   delete h;
 }
 

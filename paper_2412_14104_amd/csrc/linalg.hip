@@ -604,7 +604,7 @@ __global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int*
 // loop over its group, so every register index is static.
 __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double* R, double* Ri,
                                                          int n, int pass, int* fail,
-                                                         double shift_coef) {
+                                                         double shift_coef, int* sticky) {
   constexpr int RGP = 8, SL = 12;  // row groups and slots: 96 rows
   __shared__ double ra[2][128], re[2][128], dv[96];
   __shared__ int bad;
@@ -661,7 +661,10 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double*
   }
   __syncthreads();
   if (bad) {
-    if (tid == 0) *fail = pass + 1;  // which pass failed
+    if (tid == 0) {
+      *fail = pass + 1;  // which pass failed
+      if (sticky) atomicOr(sticky, 1);
+    }
     return;
   }
   if (q < n) {
@@ -773,7 +776,7 @@ __global__ __launch_bounds__(64) void trsm_diag_kernel(double* Xall, int64_t ldx
 // (lo, hi) (lo = 0, hi = inf disable that test).
 __global__ __launch_bounds__(256) void chol_check_kernel(const double* Lall, int n, int64_t sL,
                                                          double min_ratio, double lo, double hi,
-                                                         int* flag) {
+                                                         int* flag, int code) {
   const double* L = Lall + (int64_t)blockIdx.x * sL;
   __shared__ double mn[256], mx[256];
   __shared__ int bad[256];
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(256) void chol_check_kernel(const double* Lall, int
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && (bad[0] || !(mn[0] >= min_ratio * mx[0]))) flag[0] = 1;
+  if (threadIdx.x == 0 && (bad[0] || !(mn[0] >= min_ratio * mx[0]))) atomicOr(flag, code);
 }
 
 // Factor the (already updated) diagonal block at (j, j), jb <= 64, of every matrix of the
@@ -807,7 +810,7 @@ __global__ __launch_bounds__(256) void chol_check_kernel(const double* Lall, int
 // with coalesced loads; lane r then holds row r.  The factorisation is the right-looking
 // column algorithm (pivot from lane k, column k published through LDS); the inverse is one
 // forward substitution per lane, lane c building column c.  A pivot that is not positive
-// raises flag[0].
+// ORs 1 into flag[0].
 __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double* Dinv, int n,
                                                            int j, int jb, int* flag) {
   __shared__ double blk[64][65];
@@ -826,7 +829,7 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double*
   for (int k = 0; k < 64; ++k) {
     if (k < jb) {
       const double piv = __shfl(row[k], k, 64);
-      if (r == 0 && !(piv > 0.0)) flag[0] = 1;
+      if (r == 0 && !(piv > 0.0)) atomicOr(flag, 1);
       const double dk = (piv > 0.0) ? sqrt(piv) : __builtin_nan("");
       if (r == k) row[k] = dk;
       if (r > k) row[k] /= dk;
@@ -996,15 +999,15 @@ void trsm_right_lower_t(double* X, int64_t ldx, int64_t m, const double* L, int 
 }
 
 void chol_check(const double* L, int n, int batch, double min_ratio, double lo, double hi,
-                int* flag, hipStream_t st) {
+                int* flag, hipStream_t st, int code) {
   hipLaunchKernelGGL(chol_check_kernel, dim3(batch), dim3(256), 0, st, L, n, (int64_t)n * n,
-                     min_ratio, lo, hi, flag);
+                     min_ratio, lo, hi, flag, code);
 }
 
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
-              hipStream_t st, double shift_coef) {
+              hipStream_t st, double shift_coef, int* sticky) {
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, R, Rinv, n, pass, fail,
-                     shift_coef);
+                     shift_coef, sticky);
 }
 
 void jacobi_svd(const double* A, double* U, double* S, double* V, int n, int batch,

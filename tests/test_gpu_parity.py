@@ -234,3 +234,25 @@ def test_beta_zero_takes_the_full_cell_middle(pkg):
     _, lnzv = eng.run(0.0)
     assert abs(lnzv - math.log(2.0)) < 1e-14
     assert all(eng.swap_compressed(k) == 0 for k in range(8))
+
+
+def test_speculative_step_replays_exactly(pkg):
+    """A step that speculates on its CholeskyQR passes (no Householder fallback launched) but
+    meets a rank-deficient panel -- here the step from the initial tensor, whose panels are
+    zero-padded -- is caught at its end and replayed from its saved input: the run equals the
+    one that never speculated, bit for bit."""
+    import ctypes
+    chi, r, q, n, beta = 6, 2, 2, 6, 0.15
+    ref = pkg.Engine(chi, r, q, n, seed=0)
+    f_ref, l_ref = ref.run(beta)
+    eng = pkg.Engine(chi, r, q, n, seed=0)
+    eng.init(beta)
+    reps = ctypes.c_int64()
+    assert pkg.lib.tatrg_test_speculation(eng.handle, 1, ctypes.byref(reps)) == 0
+    for _ in range(n):
+        eng.step()
+    pkg.lib.tatrg_test_speculation(eng.handle, 0, ctypes.byref(reps))
+    f, l = eng.free_energy()
+    print("replays", reps.value, flush=True)
+    assert reps.value >= 1
+    assert f == f_ref and l == l_ref, (f, f_ref)
