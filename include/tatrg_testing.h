@@ -44,6 +44,19 @@ int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t 
                            double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
                            int64_t sC, double* ws, void* stream);
 
+/* The two contraction GEMMs chained through bf16 planes: P = A1 B1 (A1 row-major
+ * [(r1 r2)][K1], B1 row-major [K1][(c1 c2)]) is written by the split GEMM's epilogue as the
+ * three bf16 planes of P viewed as [r1][c1][(r2 c2)], and C[r1] = A2^T P[r1] (A2 row-major
+ * [(r2 c2)][M2], C row-major [R1][M2][C1]) reads them without splitting P again.  ws: at
+ * least tatrg_test_gemm_bf16x3_chain_ws(...) doubles of device memory (0 for a bad shape).
+ * Returns 0, -1 for bad arguments, -3 for a launch error. */
+size_t tatrg_test_gemm_bf16x3_chain_ws(int64_t R1, int64_t R2, int64_t C1, int64_t C2,
+                                       int64_t K1, int64_t M2);
+int tatrg_test_gemm_bf16x3_chain(const double* A1, const double* B1, const double* A2,
+                                 double* C, int64_t R1, int64_t R2, int64_t C1, int64_t C2,
+                                 int64_t K1, int64_t M2, double* ws, size_t ws_doubles,
+                                 void* stream);
+
 /* Doubles of workspace tatrg_test_tsqr needs for an m x n panel. */
 size_t tatrg_test_tsqr_ws(int64_t m, int n);
 

@@ -76,6 +76,9 @@ _SIGS = {
     "tatrg_test_gemm_bf16x3": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _i64, _i64, _i64,
                                               ctypes.c_int, ctypes.c_int, _dbl, _dbl, _i64,
                                               _i64, _i64, _i64, _p, _p]),
+    "tatrg_test_gemm_bf16x3_chain_ws": (ctypes.c_size_t, [_i64] * 6),
+    "tatrg_test_gemm_bf16x3_chain": (ctypes.c_int, [_p, _p, _p, _p] + [_i64] * 6 +
+                                     [_p, ctypes.c_size_t, _p]),
     "tatrg_test_tsqr_ws": (ctypes.c_size_t, [_i64, ctypes.c_int]),
     "tatrg_test_tsqr": (ctypes.c_int, [_p, _i64, ctypes.c_int, _i64, _p, _p, _p]),
     "tatrg_test_svd": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int, ctypes.c_int, _p]),

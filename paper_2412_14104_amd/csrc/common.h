@@ -28,15 +28,38 @@ struct GemmArgs {
 };
 void gemm_f64(const GemmArgs& g, hipStream_t st);
 
+// Planes of op(B) produced elsewhere (by a Bf16PlanesOut epilogue): p[i] is [batch][N][Kp]
+// with Kp = K rounded up to 32, zero for K <= k < Kp; stride is the batch stride in elements.
+struct Bf16PlanesIn {
+  const uint16_t* p[3];
+  int64_t stride;
+};
+// C written as its three bf16 planes, split exactly as an operand would be, instead of as
+// float64.  Element (row, col) of batch entry b, with row = r1 R2 + r2 and col = c1 C2 + c2,
+// goes to offset b stride + (r1 C1 + c1) Kp + r2 C2 + c2 of every plane: the planes of a
+// following GEMM's op(B) over K = R2 C2 with rows (r1, c1).  Offsets R2 C2 <= k < Kp of
+// the M / R2 x C1 rows of every batch entry are zeroed.  cap bounds every plane (elements).
+struct Bf16PlanesOut {
+  uint16_t* p[3];
+  int64_t R2, C1, C2, Kp, stride, cap;
+};
+
 // Split-bf16 variant: every operand is split x = x0 + x1 + x2 into bf16 planes and the six
 // products with i + j <= 2 are accumulated in fp32 on the bf16 MFMA units.  Same contract.
 // ev_after_split (optional) is recorded on st between the plane splitting and the GEMM.
-// Returns false, launching nothing, when planes_ws holds fewer than gemm_bf16x3_ws_doubles(g)
-// doubles.
+// b_in (optional) supplies op(B) as planes (g.B is then not read); c_out (optional) takes C
+// as planes (g.C is then not written; needs beta = 0, M % R2 = 0, N <= C1 C2, N % C2 = 0,
+// R2 C2 <= Kp and every offset below cap).  Returns false, launching nothing, when
+// planes_ws holds fewer than gemm_bf16x3_ws_doubles(g, b_in != nullptr) doubles or an
+// argument of b_in or c_out does not fit.
 bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
-                 hipStream_t st, hipEvent_t ev_after_split = nullptr);
-// Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes of both operands.
-size_t gemm_bf16x3_ws_doubles(const GemmArgs& g);
+                 hipStream_t st, hipEvent_t ev_after_split = nullptr,
+                 const Bf16PlanesIn* b_in = nullptr, const Bf16PlanesOut* c_out = nullptr);
+// Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes it splits (op(A) always,
+// op(B) unless it is given as planes).
+size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given = false);
+// K rounded up to the split GEMM's step of 32 (the row length of its planes).
+int64_t bf16x3_kpad(int64_t K);
 
 // C = alpha X^T Y + beta C for the skinny shapes X (K x M), Y (K x N) with M, N <= 96
 // (GemmArgs with ta && !tb, batch 1): one wave per chunk of rows writes an M x N partial

@@ -302,6 +302,12 @@ struct Carver {
   }
 };
 
+// The three bf16 planes of P, [i1][(g k4)][Kp] each with Kp = L^2 rounded up to 32, in
+// doubles.
+int64_t p_planes_doubles(const Dims& d) {
+  return (3 * d.c * d.n2 * bf16x3_kpad(d.L * d.L) * 2 + 7) / 8;
+}
+
 size_t splitk_partial_doubles(const Dims& d) {
   // Grams: up to 16 parts of n2 x n2, or 256 parts of c x c
   size_t a = 16 * (size_t)d.n2 * d.n2;
@@ -371,7 +377,8 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->Fp = cv.take(L * n3);
   h->tmp5 = cv.take(L * n4);
   h->FM4 = cv.take(L * n4);
-  h->P = cv.take(L * L * n3);
+  // P in float64; on the split path the P GEMM writes P's bf16 planes here instead
+  h->P = cv.take(std::max(L * L * n3, p_planes_doubles(d)));
   h->q1 = cv.take(std::max(L * n3, L * L * n2));  // [(i3a kA),(i2b k2)] then [(kA k2 k3), kX]
   h->q2 = cv.take(L * n4); h->q3 = cv.take(L * n4);
   h->Qt = cv.take(L * L * n2);
@@ -379,11 +386,12 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->planes_doubles = 0;
   h->planes = nullptr;
   if (h->cfg.precision == TATRG_BF16X3) {
-    // bf16 planes of the two contraction GEMMs (E.FM4 and Qt^T.P)
+    // bf16 planes the two contraction GEMMs split: E and FM4 for P = E.FM4, Qt for
+    // Qt^T.P (whose P planes come from the first GEMM's epilogue)
     GemmArgs g1 = G(c * L, L * n2, n2, nullptr, n2, false, nullptr, L * n2, false, nullptr, 0);
     GemmArgs g2 = Gb(G(n2, n2, L * L, nullptr, n2, true, nullptr, n2, false, nullptr, 0), c, 0,
                      L * L * n2, n4);
-    h->planes_doubles = std::max(gemm_bf16x3_ws_doubles(g1), gemm_bf16x3_ws_doubles(g2));
+    h->planes_doubles = std::max(gemm_bf16x3_ws_doubles(g1), gemm_bf16x3_ws_doubles(g2, true));
     h->planes = cv.take(h->planes_doubles);
   }
   h->partial_doubles = splitk_partial_doubles(d);
@@ -440,12 +448,14 @@ bool hip_ok(tatrg_handle* h, const char* where) {
 void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
 
 // The contraction GEMMs, bracketed by events when live timing is on (on the split path the
-// bracket starts after the plane splitting, so it times the GEMM kernel alone).
-void gemm_timed(tatrg_handle* h, const GemmArgs& g) {
+// bracket starts after the plane splitting, so it times the GEMM kernel alone).  b_in and
+// c_out (split path only) pass op(B) and C as bf16 planes.
+void gemm_timed(tatrg_handle* h, const GemmArgs& g, const Bf16PlanesIn* b_in = nullptr,
+                const Bf16PlanesOut* c_out = nullptr) {
   const bool on = h->profile && h->ev_used + 2 <= (int)h->ev.size();
   hipEvent_t e0 = on ? h->ev[h->ev_used] : nullptr;
   if (h->cfg.precision == TATRG_BF16X3) {
-    if (!gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0)) {
+    if (!gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0, b_in, c_out)) {
       h->err = "split-bf16 plane workspace too small for a contraction GEMM";
       h->host_fault = true;
     }
@@ -1068,10 +1078,23 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   perm(h, F, h->Fp, {c, L, c, c}, {2, 0, 1, 3});
   // tmp[(i4a k4)][(a kX g)] = S4p^T Fp
   gemm(h, G(n2, c * L * c, c, S4p, n2, true, h->Fp, c * L * c, false, h->tmp5, c * L * c));
-  // FM4[i4a][a][kX][g][k4]
-  perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
-  // P[(i1 kA)][(kX g k4)] = E[(i1 kA)][(i4a a)] FM4[(i4a a)][(kX g k4)]
-  gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
+  const bool split = h->cfg.precision == TATRG_BF16X3;
+  const int64_t Kp = bf16x3_kpad(L * L);
+  uint16_t* pp = reinterpret_cast<uint16_t*>(h->P);
+  const int64_t pn = c * n2 * Kp;  // elements per plane of P
+  if (split) {
+    // FM4[i4a][a][g][k4][kX], kX innermost: the P GEMM's columns are (g k4, kX) and its
+    // epilogue writes P's planes [i1][(g k4)][(kA kX)], K-contiguous for Qt^T.P
+    perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 4, 1, 3});
+    const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, L, n2, L, Kp, 0, pn};
+    gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, nullptr, 0),
+               nullptr, &po);
+  } else {
+    // FM4[i4a][a][kX][g][k4]
+    perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
+    // P[(i1 kA)][(kX g k4)] = E[(i1 kA)][(i4a a)] FM4[(i4a a)][(kX g k4)]
+    gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
+  }
   // Qt[kA][kX][k2][k3]
   gemm(h, G(c * L, n2, c, I, c * L, true, S2, n2, false, h->q1, n2));        // [(i3a kA),(i2b k2)]
   gemm(h, G(L * n2, n2, c, h->q1, L * n2, true, S3, n2, false, h->q2, n2));  // [(kA i2b k2),(i3b k3)]
@@ -1079,8 +1102,14 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   gemm(h, G(L * n2, L, n2, h->q3, n2, false, J, L, false, h->q1, L));        // [(kA k2 k3), kX]
   perm(h, h->q1, h->Qt, {L, c, c, L}, {0, 3, 1, 2});                        // [kA,kX,k2,k3]
   // phin[i1][(k2 k3)][(g k4)] = Qt^T P[i1]
-  gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0,
-                   L * L * n2, d.n4));
+  if (split) {
+    const Bf16PlanesIn pi = {{pp, pp + pn, pp + 2 * pn}, n2 * Kp};
+    gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, nullptr, 0, false, h->phin, n2), c, 0,
+                     0, d.n4), &pi, nullptr);
+  } else {
+    gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0,
+                     L * L * n2, d.n4));
+  }
   // rotate: [i1,k2,k3,g,k4] -> [k2,k3,k4,i1,g]
   perm(h, h->phin, out, {c, c, c, c, c}, {1, 2, 4, 0, 3});
 }

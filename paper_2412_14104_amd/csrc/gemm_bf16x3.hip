@@ -14,9 +14,12 @@
 // float64 operand is stored the other way, so the GEMM moves 16-byte vectors of 8 bf16 along
 // K for both operands and an MFMA fragment is one 16-byte LDS read.  Tiling: 512 threads
 // (8 wave64 in a 2 x 4 grid), 128 x 128 tile of C, 64 x 32 per wave as 4 x 2 MFMA blocks; K
-// advances by 32 through a three-stage LDS ring filled by direct global-to-LDS loads, so the
-// loads of the stage two steps ahead overlap the products of the current one; each plane's
-// fragments are read once and serve every product they enter.  Work-groups are ordered so
+// advances by 32 through two LDS stages filled by direct global-to-LDS loads, so the loads of
+// the next stage overlap the products of the current one (a third stage measured 2-3 %
+// slower on both contraction shapes, and two leave the LDS for staging C's planes); each
+// plane's fragments are read once and serve every product they enter.  C is written either
+// in float64 or, for a GEMM whose product is the next GEMM's op(B), directly as that
+// operand's bf16 planes (Bf16PlanesOut), so it is never stored in float64 and split again.  Work-groups are ordered so
 // that the tiles sharing a B tile run on one XCD.
 #include "common.h"
 
@@ -28,11 +31,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 32, NT = 512;
-constexpr int NSTAGE = 3;                    // LDS ring: 3 x 48 KB
+constexpr int NSTAGE = 2;                    // LDS stages: 2 x 48 KB
 constexpr int STAGE_UNITS = 2 * 3 * 8 * 64;  // 16-byte units per stage
-// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at their
-// maxima): wait until at most 6, or 0, vector-memory operations are outstanding
-constexpr unsigned WAIT_VM6 = 0x0F76u, WAIT_VM0 = 0x0F70u;
+// s_waitcnt immediate (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at their
+// maxima): wait until no vector-memory operation is outstanding
+constexpr unsigned WAIT_VM0 = 0x0F70u;
 typedef __attribute__((address_space(3))) void* lds_ptr;
 constexpr int LO_FLUSH_TILES = 4;  // float32 window of the small products: 4 x 32 values of K
 constexpr int ST = 64;             // split kernel tile (rows x K)
@@ -104,11 +107,28 @@ struct BArgs {
   const uint16_t* b[3];  // [batchB][N][Kp]
   int64_t Kp, sAp, sBp;  // plane batch strides (0 for an operand shared by the batch)
   int tiles_m, tiles_n;
+  uint16_t* cp[3];       // C as planes (Bf16PlanesOut) when cp[0] is set
+  int64_t cR2, cC1, cC2, cKp, cstride;
 };
 
+// Zero offsets [k0, Kp) of `rows` plane rows of every batch entry (the K padding of planes
+// written by a Bf16PlanesOut epilogue).
+__global__ void zero_plane_tail_kernel(uint16_t* p0, uint16_t* p1, uint16_t* p2, int64_t rows,
+                                       int64_t k0, int64_t Kp, int64_t stride) {
+  const int64_t w = Kp - k0, n = rows * w;
+  const int64_t b = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = b * stride + (i / w) * Kp + k0 + i % w;
+    p0[o] = 0;
+    p1[o] = 0;
+    p2[o] = 0;
+  }
+}
+
 // One 128 x 128 tile of C per work-group.  Operand tiles move from global memory straight
-// into LDS (global_load_lds_dwordx4, no staging registers) through a ring of NSTAGE stages of
-// BK = 32: the loads for stage kt + 2 are in flight while stage kt is multiplied.  A stage is
+// into LDS (global_load_lds_dwordx4, no staging registers) through NSTAGE = 2 stages of
+// BK = 32: the loads for step kt + 1 are in flight while stage kt is multiplied.  A stage is
 // 48 blocks of 1 KB (2 operands x 3 planes x 8 row blocks of 16 rows x 32 k); lane l of the
 // wave that fills a block writes unit l = 4 r + (c ^ (r / 4 % 4)) with the 16-byte chunk c
 // of row r, a swizzle under which the 16 lanes of each fragment read hit distinct banks.
@@ -162,20 +182,16 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
 
   const int64_t nk = Kp / BK;
   if (nk > 0) issue(0, 0);
-  if (nk > 1) issue(1, BK);
   // fragment unit of this lane: row l % 16 of a block, 16-byte chunk l / 16
   const int rl = lane & 15, fpos = rl * 4 + ((lane >> 4) ^ ((rl >> 2) & 3));
   for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt % NSTAGE);
-    // Stage kt has landed once at most the six loads of stage kt + 1 are outstanding; the
-    // barrier makes every wave's blocks visible and ends all reads of stage kt - 1, whose
-    // buffer the loads of stage kt + 2 then refill.
-    if (kt + 1 < nk)
-      __builtin_amdgcn_s_waitcnt(WAIT_VM6);
-    else
-      __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+    const int cur = (int)(kt & 1);
+    // This wave's loads of stage kt have landed; the barrier makes every wave's blocks
+    // visible and ends all reads of stage kt - 1, whose buffer the loads of step kt + 1 then
+    // refill.
+    __builtin_amdgcn_s_waitcnt(WAIT_VM0);
     __builtin_amdgcn_s_barrier();
-    if (kt + 2 < nk) issue((int)((kt + 2) % NSTAGE), (kt + 2) * BK);
+    if (kt + 1 < nk) issue((int)((kt + 1) & 1), (kt + 1) * BK);
     bf16x8 fa[3][4], fb[3][2];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -220,6 +236,54 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
 
   // D fragment of v_mfma_f32_16x16x32_bf16: lane l, element v holds row 4*(l/16) + v,
   // column l%16 of the 16 x 16 block.
+  if (ba.cp[0]) {
+    // C as planes, staged through LDS (the two operand stages are free once every wave has
+    // done its last products): each wave writes its fragments as [plane][row][col] bf16,
+    // then the work-group stores 16-byte chunks of 8 consecutive columns, which for a chunk
+    // inside one c1 group are 8 consecutive plane elements.
+    uint16_t* st16 = reinterpret_cast<uint16_t*>(&lds[0][0]);  // [3][BM][BN]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = wm * 64 + i * 16 + 4 * (lane >> 4) + v, cc = wn * 32 + j * 16 + rl;
+          const double x = g.alpha * dacc[i][j][v];
+          const uint16_t h0 = bf16_rne((float)x);
+          const double x1 = x - bf16_to_double(h0);
+          const uint16_t h1 = bf16_rne((float)x1);
+          const double x2 = x1 - bf16_to_double(h1);
+          st16[(0 * BM + rr) * BN + cc] = h0;
+          st16[(1 * BM + rr) * BN + cc] = h1;
+          st16[(2 * BM + rr) * BN + cc] = bf16_rne((float)x2);
+        }
+    __syncthreads();
+    const int64_t base = b * ba.cstride;
+    for (int q = tid; q < BM * BN / 8; q += NT) {
+      const int rr = q / (BN / 8), cc = 8 * (q % (BN / 8));
+      const int64_t row = m0 + rr, col = n0 + cc;
+      if (row >= M) continue;
+      const int64_t r1 = row / ba.cR2, r2 = row - r1 * ba.cR2;
+      const int64_t c1 = col / ba.cC2, c2 = col - c1 * ba.cC2;
+      const int64_t o = base + (r1 * ba.cC1 + c1) * ba.cKp + r2 * ba.cC2 + c2;
+      if (col + 8 <= N && c2 + 8 <= ba.cC2 && (o & 7) == 0) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          *reinterpret_cast<uint4*>(ba.cp[p] + o) =
+              *reinterpret_cast<const uint4*>(&st16[(p * BM + rr) * BN + cc]);
+      } else {
+        for (int t = 0; t < 8 && col + t < N; ++t) {
+          const int64_t ct1 = (col + t) / ba.cC2, ct2 = (col + t) - ct1 * ba.cC2;
+          const int64_t ot = base + (r1 * ba.cC1 + ct1) * ba.cKp + r2 * ba.cC2 + ct2;
+#pragma unroll
+          for (int p = 0; p < 3; ++p) ba.cp[p][ot] = st16[(p * BM + rr) * BN + cc + t];
+        }
+      }
+    }
+    return;
+  }
   double* C = g.C + b * g.sC;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -243,38 +307,68 @@ int64_t plane_batches(const GemmArgs& g, bool a_side) {
   return s == 0 ? 1 : g.batch;
 }
 
-int64_t kpad(int64_t K) { return ((K + BK - 1) / BK) * BK; }
-
 }  // namespace
 
-size_t gemm_bf16x3_ws_doubles(const GemmArgs& g) {
-  const int64_t Kp = kpad(g.K);
+int64_t bf16x3_kpad(int64_t K) { return ((K + BK - 1) / BK) * BK; }
+
+size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given) {
+  const int64_t Kp = bf16x3_kpad(g.K);
   const int64_t na = plane_batches(g, true) * g.M * Kp;
-  const int64_t nb = plane_batches(g, false) * g.N * Kp;
+  const int64_t nb = b_given ? 0 : plane_batches(g, false) * g.N * Kp;
   return (size_t)((3 * (na + nb) * 2 + 7) / 8 + 64);
 }
 
 bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
-                 hipStream_t st, hipEvent_t ev_after_split) {
+                 hipStream_t st, hipEvent_t ev_after_split, const Bf16PlanesIn* b_in,
+                 const Bf16PlanesOut* c_out) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return true;
-  // the planes of both operands must fit the workspace: launch nothing otherwise
-  if (!planes_ws || planes_ws_doubles < gemm_bf16x3_ws_doubles(g)) return false;
-  const int64_t Kp = kpad(g.K);
+  // the planes of the split operands must fit the workspace: launch nothing otherwise
+  if (!planes_ws || planes_ws_doubles < gemm_bf16x3_ws_doubles(g, b_in != nullptr))
+    return false;
+  const int64_t Kp = bf16x3_kpad(g.K);
+  if (b_in && (!b_in->p[0] || !b_in->p[1] || !b_in->p[2] || b_in->stride < 0 ||
+               (g.batch > 1 && b_in->stride > 0 && b_in->stride < g.N * Kp)))
+    return false;
+  if (c_out) {
+    const Bf16PlanesOut& o = *c_out;
+    if (!o.p[0] || !o.p[1] || !o.p[2] || g.beta != 0.0 || o.R2 < 1 || o.C2 < 1 ||
+        g.M % o.R2 != 0 || g.N % o.C2 != 0 || g.N / o.C2 > o.C1 || o.R2 * o.C2 > o.Kp ||
+        o.Kp % 8 != 0 || o.stride < 0)
+      return false;
+    // the last element of every batch entry's last plane row
+    const int64_t last = (g.batch - 1) * o.stride + ((g.M / o.R2 - 1) * o.C1 + o.C1 - 1) * o.Kp +
+                         o.Kp;
+    if (last > o.cap || (g.batch > 1 && o.stride < (g.M / o.R2) * o.C1 * o.Kp)) return false;
+  }
   const int64_t ba_n = plane_batches(g, true), bb_n = plane_batches(g, false);
-  const int64_t na = ba_n * g.M * Kp, nb = bb_n * g.N * Kp;
+  const int64_t na = ba_n * g.M * Kp, nb = b_in ? 0 : bb_n * g.N * Kp;
   // plane starts stay 16-byte aligned: na and nb are multiples of 8 elements
   uint16_t* w = reinterpret_cast<uint16_t*>(planes_ws);
   BArgs ba;
   ba.g = g;
   for (int p = 0; p < 3; ++p) {
     ba.a[p] = w + p * na;
-    ba.b[p] = w + 3 * na + p * nb;
+    ba.b[p] = b_in ? b_in->p[p] : w + 3 * na + p * nb;
+    ba.cp[p] = c_out ? c_out->p[p] : nullptr;
   }
   ba.Kp = Kp;
   ba.sAp = (ba_n == 1) ? 0 : g.M * Kp;
-  ba.sBp = (bb_n == 1) ? 0 : g.N * Kp;
+  ba.sBp = b_in ? b_in->stride : (bb_n == 1) ? 0 : g.N * Kp;
   ba.tiles_m = (int)((g.M + BM - 1) / BM);
   ba.tiles_n = (int)((g.N + BN - 1) / BN);
+  ba.cR2 = c_out ? c_out->R2 : 1;
+  ba.cC1 = c_out ? c_out->C1 : 1;
+  ba.cC2 = c_out ? c_out->C2 : 1;
+  ba.cKp = c_out ? c_out->Kp : 0;
+  ba.cstride = c_out ? c_out->stride : 0;
+  if (c_out && c_out->R2 * c_out->C2 < c_out->Kp) {
+    const int64_t rows = (g.M / c_out->R2) * c_out->C1;
+    const int64_t n = rows * (c_out->Kp - c_out->R2 * c_out->C2);
+    dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 4096), (unsigned)g.batch);
+    hipLaunchKernelGGL(zero_plane_tail_kernel, grid, dim3(256), 0, st, c_out->p[0],
+                       c_out->p[1], c_out->p[2], rows, c_out->R2 * c_out->C2, c_out->Kp,
+                       c_out->stride);
+  }
   // op(A) is M x K, stored K x M when ta.  op(B) is K x N and its planes are N x K, so the
   // float64 B is read transposed unless it is stored N x K (tb).
   {
@@ -282,7 +376,7 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
     hipLaunchKernelGGL(split3_kernel, grid, dim3(256), 0, st, g.A, g.M, g.K, g.lda, g.sA,
                        g.ta ? 1 : 0, Kp, w, w + na, w + 2 * na);
   }
-  {
+  if (!b_in) {
     dim3 grid((unsigned)((Kp + ST - 1) / ST), (unsigned)((g.N + ST - 1) / ST), (unsigned)bb_n);
     hipLaunchKernelGGL(split3_kernel, grid, dim3(256), 0, st, g.B, g.N, g.K, g.ldb, g.sB,
                        g.tb ? 0 : 1, Kp, w + 3 * na, w + 3 * na + nb, w + 3 * na + 2 * nb);

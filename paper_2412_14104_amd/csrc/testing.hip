@@ -61,6 +61,48 @@ int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t 
   return launched();
 }
 
+static bool chain_shapes_ok(int64_t R1, int64_t R2, int64_t C1, int64_t C2, int64_t K1,
+                            int64_t M2) {
+  return R1 > 0 && R2 > 0 && C1 > 0 && C2 > 0 && K1 > 0 && M2 > 0;
+}
+
+static void chain_gemms(const double* A1, const double* B1, const double* A2, double* C,
+                        int64_t R1, int64_t R2, int64_t C1, int64_t C2, int64_t K1, int64_t M2,
+                        GemmArgs* g1, GemmArgs* g2) {
+  *g1 = mk(A1, B1, nullptr, R1 * R2, C1 * C2, K1, K1, C1 * C2, 0, 0, 0, 1.0, 0.0, 1, 0, 0, 0);
+  *g2 = mk(A2, nullptr, C, M2, C1, R2 * C2, M2, 0, C1, 1, 0, 1.0, 0.0, R1, 0, 0, M2 * C1);
+}
+
+size_t tatrg_test_gemm_bf16x3_chain_ws(int64_t R1, int64_t R2, int64_t C1, int64_t C2,
+                                       int64_t K1, int64_t M2) {
+  if (!chain_shapes_ok(R1, R2, C1, C2, K1, M2)) return 0;
+  GemmArgs g1, g2;
+  chain_gemms(nullptr, nullptr, nullptr, nullptr, R1, R2, C1, C2, K1, M2, &g1, &g2);
+  const int64_t pn = R1 * C1 * bf16x3_kpad(R2 * C2);
+  return (size_t)((3 * pn * 2 + 255) / 256 * 32) +
+         std::max(gemm_bf16x3_ws_doubles(g1), gemm_bf16x3_ws_doubles(g2, true));
+}
+
+int tatrg_test_gemm_bf16x3_chain(const double* A1, const double* B1, const double* A2,
+                                 double* C, int64_t R1, int64_t R2, int64_t C1, int64_t C2,
+                                 int64_t K1, int64_t M2, double* ws, size_t ws_doubles,
+                                 void* stream) {
+  if (!A1 || !B1 || !A2 || !C || !ws || !chain_shapes_ok(R1, R2, C1, C2, K1, M2)) return -1;
+  if (ws_doubles < tatrg_test_gemm_bf16x3_chain_ws(R1, R2, C1, C2, K1, M2)) return -1;
+  GemmArgs g1, g2;
+  chain_gemms(A1, B1, A2, C, R1, R2, C1, C2, K1, M2, &g1, &g2);
+  const int64_t Kp = bf16x3_kpad(R2 * C2), pn = R1 * C1 * Kp;
+  uint16_t* pp = reinterpret_cast<uint16_t*>(ws);
+  const size_t used = (size_t)((3 * pn * 2 + 255) / 256 * 32);
+  double* rest = ws + used;
+  const size_t rest_n = ws_doubles - used;
+  const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, R2, C1, C2, Kp, 0, pn};
+  const Bf16PlanesIn pi = {{pp, pp + pn, pp + 2 * pn}, C1 * Kp};
+  if (!gemm_bf16x3(g1, rest, rest_n, (hipStream_t)stream, nullptr, nullptr, &po)) return -1;
+  if (!gemm_bf16x3(g2, rest, rest_n, (hipStream_t)stream, nullptr, &pi, nullptr)) return -1;
+  return launched();
+}
+
 size_t tatrg_test_tsqr_ws(int64_t m, int n) {
   if (n < 1 || n > 96 || m < n) return 0;
   return tsqr_ws_doubles(m, n);

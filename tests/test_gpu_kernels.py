@@ -101,6 +101,58 @@ def test_gemm_bf16x3_is_fp32_class(lib, m, n, k, ta, tb):
     assert worst < 3e-7, worst
 
 
+@pytest.mark.parametrize("R1,R2,C1,C2,K1,M2", [
+    (3, 12, 36, 12, 36, 40),     # K2 = 144: P's planes padded to 160 (zeroed tail)
+    (2, 96, 1024, 96, 64, 256),  # the contraction's shape at chi = 32 with fewer rows
+    (5, 7, 130, 9, 33, 129),     # ragged: no dimension a multiple of a tile
+])
+def test_gemm_bf16x3_chain_through_planes(lib, R1, R2, C1, C2, K1, M2):
+    """P = A1 B1 written as bf16 planes by the GEMM's epilogue and read by the next GEMM
+    (C[r1] = A2^T P[r1]) gives bit for bit what the float64 route gives: P stored in float64
+    (same kernel, columns ordered (c2, c1) so that P[r1] is a strided K x N matrix), then
+    split and multiplied; and both are within the split engine's bound of the exact product."""
+    rng = np.random.default_rng(R1 + R2 + C1 + K1)
+    a1 = rng.standard_normal((R1 * R2, K1))
+    b1 = rng.standard_normal((K1, C1 * C2))
+    a2 = rng.standard_normal((R2 * C2, M2))
+    print("case chain", R1, R2, C1, C2, K1, M2, flush=True)
+    da1, db1, da2 = dev(a1), dev(b1), dev(a2)
+    dc = torch.zeros((R1, M2, C1), dtype=torch.float64, device="cuda")
+    nws = lib.tatrg_test_gemm_bf16x3_chain_ws(R1, R2, C1, C2, K1, M2)
+    assert nws > 0
+    ws = torch.empty(nws, dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_gemm_bf16x3_chain(vp(da1), vp(db1), vp(da2), vp(dc), R1, R2, C1, C2,
+                                            K1, M2, vp(ws), nws - 1, stream()) == -1
+    assert lib.tatrg_test_gemm_bf16x3_chain(vp(da1), vp(db1), vp(da2), vp(dc), R1, R2, C1, C2,
+                                            K1, M2, vp(ws), nws, stream()) == 0
+    got = host(dc)
+    # float64 route: P64[(r1 r2)][(c2 c1)], then C[r1] = A2^T P64[r1] as [(r2 c2)][c1]
+    b1p = np.ascontiguousarray(b1.reshape(K1, C1, C2).transpose(0, 2, 1).reshape(K1, C2 * C1))
+    db1p = dev(b1p)
+    p64 = torch.zeros((R1 * R2, C2 * C1), dtype=torch.float64, device="cuda")
+    n1 = lib.tatrg_test_gemm_bf16x3_ws(R1 * R2, C2 * C1, K1, K1, C2 * C1, 0, 0, 1, 0, 0)
+    ws1 = torch.empty(n1, dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_gemm_bf16x3(vp(da1), vp(db1p), vp(p64), R1 * R2, C2 * C1, K1, K1,
+                                      C2 * C1, C2 * C1, 0, 0, 1.0, 0.0, 1, 0, 0, 0, vp(ws1),
+                                      stream()) == 0
+    ref = torch.zeros((R1, M2, C1), dtype=torch.float64, device="cuda")
+    K2 = R2 * C2
+    n2 = lib.tatrg_test_gemm_bf16x3_ws(M2, C1, K2, M2, C1, 1, 0, R1, 0, K2 * C1)
+    ws2 = torch.empty(n2, dtype=torch.float64, device="cuda")
+    assert lib.tatrg_test_gemm_bf16x3(vp(da2), vp(p64), vp(ref), M2, C1, K2, M2, C1, C1, 1, 0,
+                                      1.0, 0.0, R1, 0, K2 * C1, M2 * C1, vp(ws2), stream()) == 0
+    assert np.array_equal(got, host(ref))
+    # against the exact product: each GEMM within 3e-7 |A||B|, the second also carries the
+    # first's error through |A2|
+    p_ex = (a1 @ b1).reshape(R1, R2, C1, C2).transpose(0, 2, 1, 3).reshape(R1, C1, K2)
+    p_abs = (np.abs(a1) @ np.abs(b1)).reshape(R1, R2, C1, C2).transpose(0, 2, 1, 3).reshape(
+        R1, C1, K2)
+    for r in range(R1):
+        ex = a2.T @ p_ex[r].T
+        scale = np.abs(a2.T) @ np.abs(p_ex[r].T) + np.abs(a2.T) @ p_abs[r].T
+        assert np.all(np.abs(got[r] - ex) <= 3e-7 * scale), r
+
+
 def test_gemm_degenerate_shapes(lib):
     """K = 0 leaves beta C; M = 0 or N = 0 touches nothing (both FP64 and split-bf16)."""
     rng = np.random.default_rng(11)
