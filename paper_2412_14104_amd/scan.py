@@ -3,8 +3,8 @@
 Runs every temperature of a preset (C4: 64 values of beta in [0.140, 0.160], chi = 24,
 r = 2, q = 2, 40 steps) as batches of the library (include/tatrg.h, batch = B), all sharing
 the same Gaussian sketches.  The temperatures are dealt to `--engines` handles, each with a
-stream of its own, whose steps are issued in turn so that the device runs them concurrently
-(a step at this size is mostly chains of small latency-bound kernels).  Every temperature's
+stream and a host thread of its own, so that the device runs them concurrently (a step at
+this size is mostly chains of small latency-bound kernels).  Every temperature's
 result is that of a batch-1 run.  Prints one JSON line with the free energy per site and the
 order parameter X^(m) = (Tr A)^2 / Tr A^2 (Section 3) of every temperature, the throughput,
 and the transition estimate: for each isotropic block (m a multiple of 4, the 2^m-site
@@ -29,57 +29,86 @@ def crossing(betas, xs, level=1.5):
     return None
 
 
+def run_scan(betas, chi, r, q, n, seed=0, precision="fp64", engines=4, progress=False):
+    """Every temperature of `betas` through n RG steps, dealt in contiguous chunks to
+    `engines` handles (each a batch with its own stream).  Each handle is driven by a host
+    thread of its own: a step synchronises its stream once per temperature (the bond swap's
+    conditioning verdict), and with one thread per handle that wait never holds back the
+    other handles.  Returns the wall time between device synchronisations and, per
+    temperature, f, ln Z / V and X^(m) for m = 0..n."""
+    import threading
+
+    import torch
+    from . import BF16X3, FP64, Engine
+
+    prec = BF16X3 if precision == "bf16x3" else FP64
+    ne = max(1, min(engines, len(betas)))
+    bounds = [len(betas) * e // ne for e in range(ne + 1)]
+    chunks = [betas[bounds[e]:bounds[e + 1]] for e in range(ne)]
+    device = torch.cuda.current_device()
+    engs = []
+    for chunk in chunks:
+        st = torch.cuda.Stream()
+        eng = Engine(chi, r, q, n, seed=seed, precision=prec, record_spectra=True,
+                     batch=len(chunk), stream=st)
+        eng.init(chunk)
+        engs.append(eng)
+    torch.cuda.synchronize()
+    errors = []
+
+    def drive(e):
+        try:
+            torch.cuda.set_device(device)
+            for k in range(n):
+                engs[e].step()
+                if progress and e == 0 and k % 8 == 7:
+                    print("handle 0: step %d of %d" % (k + 1, n), file=sys.stderr, flush=True)
+        except Exception as exc:  # reported after the join
+            errors.append(exc)
+
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=drive, args=(e,)) for e in range(ne)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    f, lnzv, xs = [], [], []
+    for eng, chunk in zip(engs, chunks):
+        fe, le = eng.free_energy()
+        f += fe if isinstance(fe, list) else [fe]
+        lnzv += le if isinstance(le, list) else [le]
+        xs += [[eng.order_parameter(m, b) for m in range(n + 1)] for b in range(len(chunk))]
+    return {"seconds": seconds, "engines": ne, "f": f, "lnZV": lnzv, "X": xs}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--preset", default="C4")
     ap.add_argument("--precision", choices=["fp64", "bf16x3"], default="fp64")
     ap.add_argument("--engines", type=int, default=4,
-                    help="handles (streams) the temperatures are dealt to")
+                    help="handles (streams, host threads) the temperatures are dealt to")
     args = ap.parse_args(argv)
 
     import torch
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         return 1
-    from . import BF16X3, FP64, Engine
     from .configs import PRESETS
 
     cfg = PRESETS[args.preset]
     betas = list(cfg["betas"])
     chi, r, q, n = cfg["chi"], cfg["r"], cfg["q"], cfg["n_steps"]
-    prec = BF16X3 if args.precision == "bf16x3" else FP64
-    ne = max(1, min(args.engines, len(betas)))
-    # contiguous chunks of the temperature list, one per handle
-    bounds = [len(betas) * e // ne for e in range(ne + 1)]
-    chunks = [betas[bounds[e]:bounds[e + 1]] for e in range(ne)]
-    engines = []
-    for chunk in chunks:
-        st = torch.cuda.Stream()
-        eng = Engine(chi, r, q, n, seed=cfg["seed"], precision=prec, record_spectra=True,
-                     batch=len(chunk), stream=st)
-        eng.init(chunk)
-        engines.append(eng)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(n):
-        for eng in engines:
-            eng.step()
-        if k % 8 == 7:
-            torch.cuda.synchronize()
-            print("step %d of %d, %.1f s" % (k + 1, n, time.perf_counter() - t0),
-                  file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    gpu_s = time.perf_counter() - t0
-    f, lnzv, xs = [], [], []
-    for eng, chunk in zip(engines, chunks):
-        fe, le = eng.free_energy()
-        f += fe if isinstance(fe, list) else [fe]
-        lnzv += le if isinstance(le, list) else [le]
-        xs += [[eng.order_parameter(m, b) for m in range(n + 1)] for b in range(len(chunk))]
+    res = run_scan(betas, chi, r, q, n, cfg["seed"], args.precision, args.engines,
+                   progress=True)
+    xs = res["X"]
     est = {}
     for m in range(4, n + 1, 4):
-        c = crossing(betas, [x[m] for x in xs])
-        est[str(m)] = c
+        est[str(m)] = crossing(betas, [x[m] for x in xs])
+    gpu_s = res["seconds"]
     out = {
         "workload": "4D Ising Triad-ATRG beta scan, preset %s: %d temperatures in [%g, %g], "
                     "chi=%d, r=%d, q=%d, %d RG steps each" % (args.preset, len(betas),
@@ -87,11 +116,11 @@ def main(argv=None):
                                                              q, n),
         "precision": args.precision,
         "n_betas": len(betas),
-        "engines": ne,
+        "engines": res["engines"],
         "seconds": gpu_s,            # wall time between device synchronisations
         "rg_steps_per_s": len(betas) * n / gpu_s,
         "ms_per_rg_step": gpu_s * 1e3 / (len(betas) * n),
-        "betas": betas, "f": f, "lnZV": lnzv,
+        "betas": betas, "f": res["f"], "lnZV": res["lnZV"],
         "X_last": [x[n] for x in xs],
         "X": {str(m): [x[m] for x in xs] for m in range(0, n + 1, 4)},
         "beta_c_from_X_crossing_by_block": est,

@@ -10,6 +10,9 @@ amplifies rounding, and this measures how much for the oracle itself.  Usage:
     python tests/golden/make_sensitivity.py C4_subset   # about 50 minutes on 2 cores
         order parameter X^(m) of the three runs in C4_subset.json
         -> tests/golden/C4_subset_X_sensitivity.json
+    python tests/golden/make_sensitivity.py C4_crossing 8   # 8 worker processes
+        the same for the eight runs in C4_crossing.json
+        -> tests/golden/C4_crossing_X_sensitivity.json
     python tests/golden/make_sensitivity.py C3_one_step_k2   # about two minutes
         Phi, Psi of the one step stored in C3_one_step_k2.npz
         -> tests/golden/C3_one_step_k2_sensitivity.json
@@ -59,22 +62,29 @@ def main(name):
                              "step, written by tests/golden/make_sensitivity.py"}, fh, indent=1)
 
 
-def main_x(name):
-    g = json.load(open(os.path.join(HERE, name + ".json")))
+def x_deviation(g, run):
     chi, r, q, seed, n = g["chi"], g["r"], g["q"], g["seed"], g["n_steps"]
-    out = []
-    for run in g["runs"]:
-        rng = np.random.default_rng(NOISE_SEED)
-        phi, psi = tatrg.initial_state(run["beta"], chi)
-        dev = []
-        for k in range(n):
-            phi, psi, info = tatrg.step(phi, psi, k, chi, r, q, seed)
-            dev.append(abs(info["X"] - run["X"][k]))
-            phi = phi + NOISE * np.abs(phi).max() * rng.standard_normal(phi.shape)
-            psi = psi + NOISE * np.abs(psi).max() * rng.standard_normal(psi.shape)
-        dev.append(abs(tatrg.order_parameter(phi, psi, n) - run["X"][n]))
-        print(run["beta"], " ".join("%.1e" % d for d in dev), flush=True)
-        out.append({"beta": run["beta"], "X_dev": dev})
+    rng = np.random.default_rng(NOISE_SEED)
+    phi, psi = tatrg.initial_state(run["beta"], chi)
+    dev = []
+    for k in range(n):
+        phi, psi, info = tatrg.step(phi, psi, k, chi, r, q, seed)
+        dev.append(abs(info["X"] - run["X"][k]))
+        phi = phi + NOISE * np.abs(phi).max() * rng.standard_normal(phi.shape)
+        psi = psi + NOISE * np.abs(psi).max() * rng.standard_normal(psi.shape)
+    dev.append(abs(tatrg.order_parameter(phi, psi, n) - run["X"][n]))
+    print(run["beta"], " ".join("%.1e" % d for d in dev), flush=True)
+    return {"beta": run["beta"], "X_dev": dev}
+
+
+def main_x(name, workers=1):
+    g = json.load(open(os.path.join(HERE, name + ".json")))
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            out = list(ex.map(x_deviation, [g] * len(g["runs"]), g["runs"]))
+    else:
+        out = [x_deviation(g, run) for run in g["runs"]]
     with open(os.path.join(HERE, name + "_X_sensitivity.json"), "w") as fh:
         json.dump({"config": name, "noise": NOISE, "noise_seed": NOISE_SEED, "runs": out,
                    "source": "oracle/tatrg.py step() with 1e-15 relative noise after every "
@@ -113,8 +123,8 @@ def main_one_step(name):
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "C3"
-    if which.endswith("_subset"):
-        main_x(which)
+    if which.startswith("C4_"):
+        main_x(which, int(sys.argv[2]) if len(sys.argv) > 2 else 1)
     elif "_one_step_" in which:
         main_one_step(which)
     else:

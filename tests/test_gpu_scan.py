@@ -3,7 +3,7 @@ GPU, through the C ABI, against the FP64 oracle and exact values.
 
 X^(m) = (Tr A)^2 / Tr A^2 with A the m-th coarse tensor traced over three directions
 (Section 3, the order parameter of the transition point).  References: the oracle on small
-cases, its stored scan subset (tests/golden/C4_subset.json, written by
+cases, its stored scan runs (tests/golden/C4_subset.json, C4_crossing.json, written by
 tests/golden/make_scan_golden.py from oracle/ alone), the closed form on the initial tensor,
 brute-force partition-function ratios after untruncated steps, and beta = 0.
 """
@@ -149,3 +149,66 @@ def test_scan_subset_matches_oracle(pkg):
             worst = max(worst, abs(a - c) / bound)
             assert abs(a - c) <= bound, (b, m, a, c, bound)
         print("beta", run["beta"], "worst |dX| / bound", worst, flush=True)
+
+
+def test_threaded_scan_equals_single_runs(pkg):
+    """The scan driver deals the temperatures to several handles, each with a stream and a
+    host thread of its own; every temperature still gets the batch-1 result bit for bit."""
+    from paper_2412_14104_amd.scan import run_scan
+    chi, r, q, n = 6, 2, 2, 8
+    betas = [0.13, 0.14, 0.15, 0.16, 0.17]
+    res = run_scan(betas, chi, r, q, n, seed=0, engines=3)
+    assert res["engines"] == 3
+    for b, beta in enumerate(betas):
+        one = pkg.Engine(chi, r, q, n, seed=0)
+        f1, l1 = one.run(beta)
+        assert res["f"][b] == f1 and res["lnZV"][b] == l1, (b, res["f"][b], f1)
+        assert res["X"][b] == gpu_x(one, n)
+
+
+def test_scan_near_the_crossing_matches_oracle(pkg):
+    """Eight neighbouring temperatures of the chi = 24 scan around X = 3/2 (indices 28..35 of
+    64 in [0.140, 0.160]) through the threaded scan driver (four handles), 40 steps, against
+    the oracle's stored runs (tests/golden/C4_crossing.json).  f to REL_F, X^(m) per step to
+    max(X_TOL, 10 x the oracle's own drift under 1e-15 noise per step,
+    C4_crossing_X_sensitivity.json), and the transition estimate of every block level m:
+    the crossing of X = 3/2 by linear interpolation lies between the same two temperatures,
+    and moves by no more than the X bounds of its two end points allow."""
+    from paper_2412_14104_amd.scan import crossing, run_scan
+    path = os.path.join(HERE, "golden", "C4_crossing.json")
+    spath = os.path.join(HERE, "golden", "C4_crossing_X_sensitivity.json")
+    if not os.path.exists(path) or not os.path.exists(spath):
+        pytest.skip("golden C4_crossing or its X sensitivity not generated")
+    with open(path) as fh:
+        g = json.load(fh)
+    with open(spath) as fh:
+        sens = json.load(fh)["runs"]
+    betas = [run["beta"] for run in g["runs"]]
+    n = g["n_steps"]
+    print("case C4 crossing", betas, flush=True)
+    res = run_scan(betas, g["chi"], g["r"], g["q"], n, seed=g["seed"], engines=4)
+    bounds = []
+    for b, run in enumerate(g["runs"]):
+        assert abs(res["f"][b] - run["f"]) <= REL_F * abs(run["f"]), (b, res["f"][b], run["f"])
+        assert abs(res["lnZV"][b] - run["lnZV"]) <= REL_F * abs(run["lnZV"])
+        assert sens[b]["beta"] == run["beta"]
+        bd = [max(X_TOL, 10.0 * d) for d in sens[b]["X_dev"]]
+        for m, (a, c) in enumerate(zip(res["X"][b], run["X"])):
+            assert abs(a - c) <= bd[m], (b, m, a, c, bd[m])
+        bounds.append(bd)
+    found = 0
+    for m in range(4, n + 1, 4):
+        xo = [run["X"][m] for run in g["runs"]]
+        xg = [x[m] for x in res["X"]]
+        co, cg = crossing(betas, xo), crossing(betas, xg)
+        if co is None:
+            continue
+        found += 1
+        assert cg is not None, m
+        i = next(j for j in range(len(betas) - 1)
+                 if (xo[j] - 1.5) * (xo[j + 1] - 1.5) <= 0 and xo[j] != xo[j + 1])
+        slope = abs(xo[i + 1] - xo[i]) / (betas[i + 1] - betas[i])
+        tol = (bounds[i][m] + bounds[i + 1][m]) / slope + 1e-15
+        print("m", m, "beta_c", cg, "oracle", co, "tol", tol, flush=True)
+        assert abs(cg - co) <= tol, (m, cg, co, tol)
+    assert found >= 1
