@@ -139,6 +139,22 @@ tatrg_status tatrg_lognorm(tatrg_handle* h, double* h_acc);
  * (including a non-positive final trace). */
 tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
 
+/* Synchronising; valid after n_steps steps (ESTATE otherwise), on a handle whose batch holds
+ * triples of temperatures (beta_i - d_i, beta_i, beta_i + d_i), i = 0 .. batch/3 - 1, in
+ * that order (tatrg_init_tensor; EINVAL for a batch that is not a multiple of 3 or a triple
+ * that is not symmetric to 1e-9 of its spacing).  The derivatives of ln Z / V (Section 3,
+ * Z = tTr prod T with the bond weight e^{beta s s'} of W) in beta by central differences:
+ *   h_d1[i] = (L+ - L-) / (2 d_i)                      u = -h_d1 is the internal energy per site
+ *   h_d2[i] = (L+ - 2 L0 + L-) / d_i^2 (nonuniform form)  c = beta^2 h_d2 is the specific heat
+ * with L = ln Z / V of the three runs, and h_lnzv[i] = L0.  The Gaussian sketches do not
+ * depend on beta, so the three runs share them and ln Z / V of the truncated RG is a smooth
+ * function of beta between changes of the truncation; with d ~ 1e-4 the difference error
+ * is ~d^2 of the third derivative and the rounding error ~1e-15 / d.  Output arrays (host,
+ * batch / 3 entries each) may be NULL.  Leaves the state unchanged (as tatrg_free_energy);
+ * ENUMERIC when a fault has been flagged. */
+tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1,
+                                   double* h_d2);
+
 /* Synchronising.  Per-step records of temperature b (0 <= b < batch), kept when
  * record_spectra != 0, for step = 0..n_steps (step n_steps is recorded by
  * tatrg_free_energy):

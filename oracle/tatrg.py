@@ -492,6 +492,19 @@ def run(beta, chi, r, q, seed, n_steps, w=None, record=True):
             "X_final": x_n}
 
 
+def lnz_derivatives(beta, delta, chi, r, q, seed, n_steps):
+    """d(ln Z/V)/d beta and d^2(ln Z/V)/d beta^2 of the truncated RG by central differences
+    at beta - delta, beta, beta + delta (Z of Section 3; u = -d(ln Z/V)/d beta is the internal
+    energy per site, c = beta^2 d^2(ln Z/V)/d beta^2 the specific heat).  The sketches do not
+    depend on beta (READING: beta is not in the generator's key), so the three runs share them
+    and ln Z/V is a smooth function of beta between truncation changes.
+    Returns (ln Z/V at beta, first derivative, second derivative)."""
+    lm = run(beta - delta, chi, r, q, seed, n_steps, record=False)["lnZV"]
+    l0 = run(beta, chi, r, q, seed, n_steps, record=False)["lnZV"]
+    lp = run(beta + delta, chi, r, q, seed, n_steps, record=False)["lnZV"]
+    return l0, (lp - lm) / (2.0 * delta), (lp - 2.0 * l0 + lm) / (delta * delta)
+
+
 def run_partial(beta, chi, r, q, seed, n_steps, w=None):
     """First n_steps steps only: returns (Phi, Psi, sum_{k<n} 2^-k ln c_k)."""
     phi, psi = initial_state(beta, chi, w)

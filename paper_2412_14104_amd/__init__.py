@@ -60,6 +60,7 @@ _SIGS = {
                                           _p, _p, _p, _p]),
     "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
     "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
+    "tatrg_lnz_derivatives": (ctypes.c_int, [_p, _dblp, _dblp, _dblp]),
     "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),
     "tatrg_get_record": (ctypes.c_int, [_p, _i32, _i32, _i32, _dblp, _i32,
                                         ctypes.POINTER(_i32)]),
@@ -79,6 +80,7 @@ _SIGS = {
     "tatrg_test_gemm_bf16x3_chain_ws": (ctypes.c_size_t, [_i64] * 6),
     "tatrg_test_gemm_bf16x3_chain": (ctypes.c_int, [_p, _p, _p, _p] + [_i64] * 6 +
                                      [_p, ctypes.c_size_t, _p]),
+    "tatrg_test_split_products": (ctypes.c_int, [ctypes.c_int]),
     "tatrg_test_tsqr_ws": (ctypes.c_size_t, [_i64, ctypes.c_int]),
     "tatrg_test_tsqr": (ctypes.c_int, [_p, _i64, ctypes.c_int, _i64, _p, _p, _p]),
     "tatrg_test_svd": (ctypes.c_int, [_p, _p, _p, _p, ctypes.c_int, ctypes.c_int, _p]),
@@ -166,6 +168,14 @@ class Engine:
         if self.batch == 1:
             return f[0], lnzv[0]
         return list(f), list(lnzv)
+
+    def lnz_derivatives(self):
+        """For a batch of triples (beta - d, beta, beta + d): lists (ln Z/V, d(ln Z/V)/d beta,
+        d^2(ln Z/V)/d beta^2) of batch / 3 entries (tatrg_lnz_derivatives)."""
+        n = self.batch // 3
+        l0, d1, d2 = ((ctypes.c_double * max(n, 1))() for _ in range(3))
+        _check(lib.tatrg_lnz_derivatives(self.handle, l0, d1, d2), self.handle)
+        return list(l0[:n]), list(d1[:n]), list(d2[:n])
 
     def spectrum(self, step, which, b=0):
         buf = (ctypes.c_double * self.chi)()

@@ -1654,6 +1654,38 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv) {
   return s;
 }
 
+tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1,
+                                   double* h_d2) {
+  if (!h) return TATRG_EINVAL;
+  const int nb = h->cfg.batch;
+  if (nb % 3 != 0) {
+    h->err = "lnz_derivatives needs the batch as triples (beta - d, beta, beta + d)";
+    return TATRG_EINVAL;
+  }
+  if (h->initialized) {
+    for (int i = 0; i < nb / 3; ++i) {
+      const double bm = h->betas[3 * i], b0 = h->betas[3 * i + 1], bp = h->betas[3 * i + 2];
+      const double dm = b0 - bm, dp = bp - b0;
+      // a symmetric triple: the central differences below are then second-order accurate
+      if (!(dm > 0.0 && dp > 0.0) || std::fabs(dp - dm) > 1e-9 * (dp + dm)) {
+        h->err = "lnz_derivatives: temperatures 3i, 3i+1, 3i+2 must be beta - d, beta, beta + d";
+        return TATRG_EINVAL;
+      }
+    }
+  }
+  std::vector<double> l(nb);
+  const tatrg_status s = tatrg_free_energy(h, nullptr, l.data());
+  if (s != TATRG_OK && s != TATRG_ENUMERIC) return s;
+  for (int i = 0; i < nb / 3; ++i) {
+    const double bm = h->betas[3 * i], b0 = h->betas[3 * i + 1], bp = h->betas[3 * i + 2];
+    const double lm = l[3 * i], l0 = l[3 * i + 1], lp = l[3 * i + 2];
+    if (h_lnzv) h_lnzv[i] = l0;
+    if (h_d1) h_d1[i] = (lp - lm) / (bp - bm);
+    if (h_d2) h_d2[i] = 2.0 * ((lp - l0) / (bp - b0) - (l0 - lm) / (b0 - bm)) / (bp - bm);
+  }
+  return s;
+}
+
 tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,
                               double* h_out, int32_t cap, int32_t* n_out) {
   if (!h || !h_out || !n_out || cap < 1) return TATRG_EINVAL;

@@ -1,0 +1,97 @@
+"""Derivatives of ln Z / V in beta on the GPU (tatrg_lnz_derivatives and the autograd
+function over it) against exact enumeration and the oracle's stored central differences.
+
+u = -d(ln Z/V)/d beta and c = beta^2 d^2(ln Z/V)/d beta^2 of Z = tTr prod T (Section 3).
+References: the cumulants of the bond sum on small periodic lattices by enumeration
+(tests/bond_moments.py), where the RG is untruncated, and tests/golden/FD.json (written by
+tests/golden/make_fd_golden.py from oracle/ alone) for the presets C1 and C2.
+"""
+import json
+import os
+
+import pytest
+
+from bond_moments import bond_moments
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2412_14104_amd as p
+    return p
+
+
+@pytest.mark.parametrize("beta,extents,chi,r,n", [(0.15, (2, 1, 1, 1), 4, 4, 1),
+                                                  (0.4, (2, 1, 1, 1), 4, 4, 1),
+                                                  (0.1496947, (2, 2, 1, 1), 16, 2, 2)])
+def test_derivatives_exact_untruncated(pkg, beta, extents, chi, r, n):
+    """Untruncated runs: the first derivative equals <E>/V within the central difference's
+    h^2 k3 / 6, the second Var(E)/V to 1e-6."""
+    from paper_2412_14104_amd.energy import derivatives
+    h = 1e-4
+    m, var, k3 = bond_moments(beta, extents)
+    print("case exact", beta, extents, chi, r, n, flush=True)
+    l0, d1, d2 = derivatives([beta], chi, r, 2, n, delta=h)
+    assert abs(d1[0] - m) < h * h * abs(k3) / 6 * 1.1 + 1e-10, (d1, m)
+    assert abs(d2[0] - var) < 1e-6, (d2, var)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_derivatives_match_oracle_fd(pkg, name):
+    """C1 (chi = 6, 16 steps) and C2 (chi = 16, 40 steps): ln Z/V to 1e-9 relative and
+    d(ln Z/V)/d beta to the 1e-5 relative bar against the oracle's central differences at the
+    same h = 1e-4; the FP64 paths agree to ~1e-15 in ln Z/V, i.e. ~1e-11 in the first and
+    ~1e-7 in the second difference, so the second derivative is held to 1e-4 relative."""
+    from paper_2412_14104_amd.energy import derivatives
+    with open(os.path.join(HERE, "golden", "FD.json")) as fh:
+        g = json.load(fh)
+    case = next(c for c in g["cases"] if c["config"] == name)
+    print("case FD", name, case["beta"], flush=True)
+    l0, d1, d2 = derivatives([case["beta"]], case["chi"], case["r"], case["q"],
+                             case["n_steps"], case["seed"], g["delta"])
+    assert abs(l0[0] - case["lnZV"]) <= 1e-9 * abs(case["lnZV"])
+    e1 = abs(d1[0] - case["dlnZV_dbeta"]) / abs(case["dlnZV_dbeta"])
+    e2 = abs(d2[0] - case["d2lnZV_dbeta2"]) / abs(case["d2lnZV_dbeta2"])
+    print(name, "relative error d1 %.2e d2 %.2e" % (e1, e2), flush=True)
+    assert e1 <= 1e-5 and e2 <= 1e-4, (d1, d2, case)
+
+
+def test_autograd_function_gives_the_derivative(pkg):
+    """backward of LnZ multiplies the incoming gradient by the derivative the forward batch
+    computed (C1 sizes, 16 steps)."""
+    from paper_2412_14104_amd.energy import LnZ, derivatives
+    beta = torch.tensor(0.15, dtype=torch.float64, requires_grad=True)
+    lnz = LnZ.apply(beta, 6, 2, 2, 16)
+    (3.0 * lnz).backward()
+    l0, d1, _ = derivatives([0.15], 6, 2, 2, 16)
+    assert lnz.item() == l0[0]
+    assert beta.grad.item() == 3.0 * d1[0]
+
+
+def test_triples_are_validated(pkg):
+    eng = pkg.Engine(4, 2, 2, 2, batch=2)
+    eng.init([0.1, 0.2])
+    for _ in range(2):
+        eng.step()
+    with pytest.raises(pkg.TatrgError):
+        eng.lnz_derivatives()
+    eng = pkg.Engine(4, 2, 2, 2, batch=3)
+    eng.init([0.1, 0.2, 0.35])
+    for _ in range(2):
+        eng.step()
+    with pytest.raises(pkg.TatrgError):
+        eng.lnz_derivatives()
+    eng = pkg.Engine(4, 2, 2, 2, batch=3)
+    eng.init([0.1, 0.2, 0.3])
+    with pytest.raises(pkg.TatrgError):  # before n_steps steps
+        eng.lnz_derivatives()
+    for _ in range(2):
+        eng.step()
+    l0, d1, d2 = eng.lnz_derivatives()
+    assert len(l0) == 1 and d1[0] > 0

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
+from bond_moments import bond_moments
 from oracle import bruteforce as bf
 from oracle import philox
 from oracle import tatrg as t
@@ -423,3 +424,19 @@ def test_triad_with_fewer_internal_lines_truncates():
     tr = t.run(BETA_C, 6, 2, 2, 0, 4, record=False)
     at = atrg.run(BETA_C, 6, 2, 0, 4)
     assert abs(tr["f"] - at["f"]) > 1e-8 * abs(at["f"])
+
+
+@pytest.mark.parametrize("beta,extents,chi,r,n", [(0.15, (2, 1, 1, 1), 4, 4, 1),
+                                                  (0.4, (2, 1, 1, 1), 4, 4, 1),
+                                                  (BETA_C, (2, 2, 1, 1), 16, 2, 2)])
+def test_lnz_derivatives_exact(beta, extents, chi, r, n):
+    """Central differences (h = 1e-4) of untruncated runs reproduce the exact cumulants of
+    the bond sum: d(ln Z/V)/d beta = <E>/V within the difference's h^2 k3 / 6 error, and the
+    second derivative Var(E)/V to 1e-6."""
+    h = 1e-4
+    m, var, k3 = bond_moments(beta, extents)
+    l0, d1, d2 = t.lnz_derivatives(beta, h, chi, r, 2, 0, n)
+    v = int(np.prod(extents))
+    assert abs(l0 - bf.ising_lnz_bruteforce(beta, extents) / v) < 1e-12
+    assert abs(d1 - m) < h * h * abs(k3) / 6 * 1.1 + 1e-10, (d1, m)
+    assert abs(d2 - var) < 1e-6, (d2, var)
