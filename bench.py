@@ -180,6 +180,9 @@ def main():
     ap.add_argument("--no-finish", action="store_true",
                     help="skip the untimed rest of the 40-step run and the free energy (for "
                          "short profiler runs)")
+    ap.add_argument("--split-products", type=int, choices=[3, 6], default=6,
+                    help="products per split GEMM: 6 (the engine) or 3 (accuracy ablation, "
+                         "i + j <= 1)")
     ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
                     help="only copy a MIB-sized float64 device buffer three times (a plain "
                          "copy of known size, to calibrate rocprofv3's HBM byte counters) "
@@ -212,6 +215,8 @@ def main():
     import paper_2412_14104_amd as pkg
     from paper_2412_14104_amd.configs import PRESETS
 
+    if args.split_products != 6:
+        pkg.lib.tatrg_test_split_products(args.split_products)
     cfg = PRESETS["C3"]
     chi, r, q, seed = cfg["chi"], cfg["r"], cfg["q"], cfg["seed"]
     beta = cfg["betas"][0]
@@ -232,17 +237,20 @@ def main():
     peak = BF16_PEAK_TFLOPS if split else FP64_PEAK_TFLOPS
     roofline = {"bound": "mfma", "achieved": alg, "peak": peak, "unit": "TFLOP/s",
                 "frac": alg / peak,
-                "traffic": profiled_value("traffic_bytes_per_launch") if split else None,
+                "traffic": (profiled_value("traffic_bytes_per_launch")
+                            if split and args.split_products == 6 else None),
                 "kernel": "gemm_bf16x3_kernel: contraction GEMMs P = E.FM4 and Phi = Qt^T.P "
                           "(both halves)" if split else
                           "gemm_f64_kernel: contraction GEMMs P = E.FM4 and Phi = Qt^T.P",
                 "launches": launches, "flops_per_launch": main_run["flops_per_launch"],
                 "avg_launch_ms": avg_launch_s * 1e3}
     if split:
-        # the split product issues six bf16 x bf16 MFMA products per multiply-add of the method
-        roofline["bf16_issue_tflops"] = 6 * alg
-        roofline["bf16_issue_frac"] = 6 * alg / BF16_PEAK_TFLOPS
-        roofline["mfma_busy_frac"] = profiled_value("mfma_busy_frac")
+        # the split product issues six (three in the ablation) bf16 x bf16 MFMA products per
+        # multiply-add of the method
+        roofline["bf16_issue_tflops"] = args.split_products * alg
+        roofline["bf16_issue_frac"] = args.split_products * alg / BF16_PEAK_TFLOPS
+        roofline["mfma_busy_frac"] = (profiled_value("mfma_busy_frac")
+                                      if args.split_products == 6 else None)
     sm = main_run["stage_ms_per_step"]
     names = ["S0", "S1", "S2", "S3", "S4", "S5"]
     fam_flops = sum(stages[k] for k in ("S1", "S2", "S3", "S4"))
@@ -273,7 +281,7 @@ def main():
         "config": {"workload": "4D Ising Triad-ATRG, chi=32, r=3 (L=96), q=2, "
                                "beta=0.1496947, seed 0, RG steps %d" % n_total,
                    "chi": chi, "r": r, "q": q, "beta": beta, "n_steps": n_total,
-                   "precision": args.precision},
+                   "precision": args.precision, "split_products": args.split_products},
         "roofline": roofline,
         "roofline_fp64_stages": roofline_fp64,
         "swap_compressed_timed_steps": main_run["swap_compressed_timed_steps"],

@@ -44,6 +44,12 @@ int tatrg_test_gemm_bf16x3(const double* A, const double* B, double* C, int64_t 
                            double alpha, double beta, int64_t batch, int64_t sA, int64_t sB,
                            int64_t sC, double* ws, void* stream);
 
+/* Accuracy ablation of the split-bf16 engine: every split GEMM launched afterwards, in any
+ * handle of the process, runs n = 3 products (i + j <= 1, about 2^-16 of |A||B|) or n = 6
+ * (i + j <= 2, the engine's default, about 2^-24).  Returns the previous count, -1 for any
+ * other n.  Not for concurrent use with running steps. */
+int tatrg_test_split_products(int n);
+
 /* The two contraction GEMMs chained through bf16 planes: P = A1 B1 (A1 row-major
  * [(r1 r2)][K1], B1 row-major [K1][(c1 c2)]) is written by the split GEMM's epilogue as the
  * three bf16 planes of P viewed as [r1][c1][(r2 c2)], and C[r1] = A2^T P[r1] (A2 row-major

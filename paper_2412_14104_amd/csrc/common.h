@@ -60,6 +60,9 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given = false);
 // K rounded up to the split GEMM's step of 32 (the row length of its planes).
 int64_t bf16x3_kpad(int64_t K);
+// Products every later split GEMM runs: 6 (the engine) or 3 (i + j <= 1, an accuracy
+// ablation).  Returns the previous count, -1 for another n.  Process-wide.
+int set_split_products(int n);
 
 // C = alpha X^T Y + beta C for the skinny shapes X (K x M), Y (K x N) with M, N <= 96
 // (GemmArgs with ta && !tb, batch 1): one wave per chunk of rows writes an M x N partial

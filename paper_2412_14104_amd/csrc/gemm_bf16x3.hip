@@ -21,6 +21,8 @@
 // in float64 or, for a GEMM whose product is the next GEMM's op(B), directly as that
 // operand's bf16 planes (Bf16PlanesOut), so it is never stored in float64 and split again.  Work-groups are ordered so
 // that the tiles sharing a B tile run on one XCD.
+#include <atomic>
+
 #include "common.h"
 
 namespace tatrg {
@@ -107,6 +109,7 @@ struct BArgs {
   const uint16_t* b[3];  // [batchB][N][Kp]
   int64_t Kp, sAp, sBp;  // plane batch strides (0 for an operand shared by the batch)
   int tiles_m, tiles_n;
+  int group_m;           // rows of tiles per group of the tile order (0: M fastest throughout)
   uint16_t* cp[3];       // C as planes (Bf16PlanesOut) when cp[0] is set
   int64_t cR2, cC1, cC2, cKp, cstride;
 };
@@ -132,6 +135,9 @@ __global__ void zero_plane_tail_kernel(uint16_t* p0, uint16_t* p1, uint16_t* p2,
 // 48 blocks of 1 KB (2 operands x 3 planes x 8 row blocks of 16 rows x 32 k); lane l of the
 // wave that fills a block writes unit l = 4 r + (c ^ (r / 4 % 4)) with the 16-byte chunk c
 // of row r, a swizzle under which the 16 lanes of each fragment read hit distinct banks.
+// NPROD = 6 is the engine (all products with i + j <= 2); NPROD = 3 keeps only i + j <= 1,
+// an ablation of the split's accuracy (about 2^-16 of |A||B| instead of 2^-24).
+template <int NPROD>
 __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
   const GemmArgs& g = ba.g;
   __shared__ __attribute__((aligned(1024))) uint4 lds[NSTAGE][STAGE_UNITS];
@@ -140,11 +146,23 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
   const int wm = wave >> 2, wn = wave & 3;
   const int64_t b = blockIdx.z;
   // XCD-aware order: work-group w runs on XCD w % 8; tiles are numbered so that each XCD
-  // gets a contiguous range, M fastest, i.e. the tiles that share a B tile.
+  // gets a contiguous range.  Within it the tiles run M fastest (those that share a B tile),
+  // in groups of group_m rows of tiles when there are many: the ~32 tiles an XCD runs at once
+  // then share A tiles as well as B tiles in its L2 (6 x 5 rather than 24 x 1 for P = E.FM4,
+  // measured 5 % faster there).
   const int nt = ba.tiles_m * ba.tiles_n;
   int w = blockIdx.x;
   if (nt % 8 == 0) w = (w % 8) * (nt / 8) + w / 8;
-  const int tm = w % ba.tiles_m, tn = w / ba.tiles_m;
+  int tm, tn;
+  if (ba.group_m > 0) {
+    const int per = ba.group_m * ba.tiles_n, grp = w / per, fm = grp * ba.group_m;
+    const int gs = min(ba.tiles_m - fm, ba.group_m), r = w - grp * per;
+    tm = fm + r % gs;
+    tn = r / gs;
+  } else {
+    tm = w % ba.tiles_m;
+    tn = w / ba.tiles_m;
+  }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int64_t M = g.M, N = g.N, Kp = ba.Kp;
 
@@ -210,9 +228,11 @@ __global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(BArgs ba) {
         hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], hi[i][j], 0, 0, 0);
         lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], lo[i][j], 0, 0, 0);
         lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], lo[i][j], 0, 0, 0);
-        lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[1][j], lo[i][j], 0, 0, 0);
-        lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[2][j], lo[i][j], 0, 0, 0);
-        lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[0][j], lo[i][j], 0, 0, 0);
+        if (NPROD == 6) {
+          lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[1][j], lo[i][j], 0, 0, 0);
+          lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[2][j], lo[i][j], 0, 0, 0);
+          lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[0][j], lo[i][j], 0, 0, 0);
+        }
       }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -309,6 +329,14 @@ int64_t plane_batches(const GemmArgs& g, bool a_side) {
 
 }  // namespace
 
+// Products per split GEMM (6; 3 for the accuracy ablation), process-wide.
+static std::atomic<int> g_split_products{6};
+
+int set_split_products(int n) {
+  if (n != 3 && n != 6) return -1;
+  return g_split_products.exchange(n);
+}
+
 int64_t bf16x3_kpad(int64_t K) { return ((K + BK - 1) / BK) * BK; }
 
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given) {
@@ -356,6 +384,7 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
   ba.sBp = b_in ? b_in->stride : (bb_n == 1) ? 0 : g.N * Kp;
   ba.tiles_m = (int)((g.M + BM - 1) / BM);
   ba.tiles_n = (int)((g.N + BN - 1) / BN);
+  ba.group_m = ba.tiles_m >= 12 ? 6 : 0;
   ba.cR2 = c_out ? c_out->R2 : 1;
   ba.cC1 = c_out ? c_out->C1 : 1;
   ba.cC2 = c_out ? c_out->C2 : 1;
@@ -383,7 +412,10 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
   }
   if (ev_after_split) (void)hipEventRecord(ev_after_split, st);
   dim3 grid((unsigned)(ba.tiles_m * ba.tiles_n), 1u, (unsigned)g.batch);
-  hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(NT), 0, st, ba);
+  if (g_split_products == 3)
+    hipLaunchKernelGGL(gemm_bf16x3_kernel<3>, grid, dim3(NT), 0, st, ba);
+  else
+    hipLaunchKernelGGL(gemm_bf16x3_kernel<6>, grid, dim3(NT), 0, st, ba);
   return true;
 }
 

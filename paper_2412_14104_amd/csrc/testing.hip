@@ -103,6 +103,8 @@ int tatrg_test_gemm_bf16x3_chain(const double* A1, const double* B1, const doubl
   return launched();
 }
 
+int tatrg_test_split_products(int n) { return set_split_products(n); }
+
 size_t tatrg_test_tsqr_ws(int64_t m, int n) {
   if (n < 1 || n > 96 || m < n) return 0;
   return tsqr_ws_doubles(m, n);

@@ -153,6 +153,32 @@ def test_gemm_bf16x3_chain_through_planes(lib, R1, R2, C1, C2, K1, M2):
         assert np.all(np.abs(got[r] - ex) <= 3e-7 * scale), r
 
 
+def test_gemm_bf16x3_three_product_ablation(lib):
+    """With three products (i + j <= 1) the dropped terms are about 2^-16 of |A||B|: the
+    error grows by orders of magnitude over the six-product engine but stays below
+    3 x 2^-16; the engine's default comes back afterwards."""
+    rng = np.random.default_rng(17)
+    m, n, k = 256, 192, 4096
+    a = rng.standard_normal((m, k))
+    b = rng.standard_normal((k, n))
+    da, db = dev(a), dev(b)
+    ref = a @ b
+    scale = np.abs(a) @ np.abs(b)
+    nws = lib.tatrg_test_gemm_bf16x3_ws(m, n, k, k, n, 0, 0, 1, 0, 0)
+    ws = torch.empty(nws, dtype=torch.float64, device="cuda")
+    worst = {}
+    for nprod in (3, 6):
+        assert lib.tatrg_test_split_products(nprod) in (3, 6)
+        dc = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+        assert lib.tatrg_test_gemm_bf16x3(vp(da), vp(db), vp(dc), m, n, k, k, n, n, 0, 0, 1.0,
+                                          0.0, 1, 0, 0, 0, vp(ws), stream()) == 0
+        worst[nprod] = (np.abs(host(dc) - ref) / scale).max()
+    assert lib.tatrg_test_split_products(5) == -1
+    assert lib.tatrg_test_split_products(6) == 6
+    print("worst |C - AB| / (|A||B|): 3 products", worst[3], "6 products", worst[6], flush=True)
+    assert worst[6] < 3e-7 and 100 * worst[6] < worst[3] < 3 * 2.0 ** -16, worst
+
+
 def test_gemm_degenerate_shapes(lib):
     """K = 0 leaves beta C; M = 0 or N = 0 touches nothing (both FP64 and split-bf16)."""
     rng = np.random.default_rng(11)
