@@ -141,8 +141,7 @@ int tatrg_profile_read(struct tatrg_handle* h, double* total_ms, int32_t* launch
 int tatrg_test_speculation(struct tatrg_handle* h, int on, int64_t* replays);
 
 /* Stage timing of the profiled steps (tatrg_profile_enable also reserves events at the stage
- * boundaries of up to ceil(max_launches / 4) steps, on the handle's stream, which the lanes
- * rejoin before each boundary).  Synchronises; stage_ms[0..5] (host) receives the summed
+ * boundaries of up to ceil(max_launches / 4) steps, on the handle's stream).  Synchronises; stage_ms[0..5] (host) receives the summed
  * device time of canonical form (S0, Section 2), bond swap (S1, Eq. (1)), isometries (S2,
  * Eqs. (2)-(3)), triad tensors (S3, Eqs. (4)-(11)), squeezers (S4) and contraction with the
  * slot rotation (S5, Eqs. (makeMG)/(makeMH)); *steps the number of steps timed.  Clears the

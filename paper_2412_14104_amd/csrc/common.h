@@ -19,9 +19,11 @@ struct GemmArgs {
   double alpha, beta;
   int64_t batch;
   // Optional device-side predicate: when `cond` is set the launch does nothing unless
-  // (*cond != 0) == cond_when (lets a fallback path be launched without a host sync).
+  // (*cond != 0) == cond_when (lets a fallback path be launched without a host sync).  With
+  // cond_stride > 0 (gemm_f64 and its split-K form) batch entry b reads cond[b * cond_stride].
   const int* cond = nullptr;
   bool cond_when = false;
+  int64_t cond_stride = 0;
   // Symmetric output (op(A) op(B) = X X^T with M = N): split-K computes the tiles on and
   // above the diagonal only and its reduction mirrors them.
   bool sym = false;
@@ -90,8 +92,10 @@ void tsqr(double* Y, int64_t m, int n, int64_t ld, double* R_out, double* ws, hi
 // largest diagonal entry; pass 2 (G close to the identity) when a pivot leaves (0.25, 4).  A
 // failure sets *fail = pass + 1 (and, when sticky is given, ORs 1 into *sticky) and leaves
 // R, Rinv unwritten.  Does nothing when *fail is already set.
+// batch > 1 factors `batch` Grams (strides sG, sR, sRi) with their own flags fail[b * sf].
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
-              hipStream_t st, double shift_coef = 0.0, int* sticky = nullptr);
+              hipStream_t st, double shift_coef = 0.0, int* sticky = nullptr, int batch = 1,
+              int64_t sG = 0, int64_t sR = 0, int64_t sRi = 0, int sf = 0);
 
 // Solves X L^T = B in place for `batch` tall panels X (m x n, leading dim ldx, stride sX)
 // with lower-triangular L (n x n, stride sL): column blocks of 64, each a GEMM update by the

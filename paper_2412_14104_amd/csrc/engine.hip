@@ -222,21 +222,13 @@ struct tatrg_handle {
   double *Smat;
   double *s, *sig, *Rp, *Rs, *Cc, *Uc, *Vc, *Oc, *Pm, *Pm0, *RbT, *Rb, *Uh, *Sh, *Vh, *Dm;
   double *Ssq, *Usq, *Vsq, *Umat, *Vmat;
-  // Lanes: a stream of their own plus the scratch an independent chi^2-row RSVD needs, so the
-  // four isometry RSVDs (latency-bound chains of small factorisations) run concurrently.
-  struct Lane {
-    hipStream_t st = nullptr;
-    hipEvent_t done = nullptr;
-    double *Pb = nullptr, *P3 = nullptr, *Gq = nullptr, *tsqr_ws = nullptr, *partial = nullptr;
-    size_t partial_doubles = 0;
-    int* flag = nullptr;
-    // squeezer RSVD and its factors (chi^2-row panels, w x w core, chi-column factors)
-    double *Pa = nullptr, *Cm = nullptr, *RbT = nullptr, *Rb = nullptr, *Uh = nullptr;
-    double *Sh = nullptr, *Vh = nullptr, *Usq = nullptr, *Vsq = nullptr, *Umat = nullptr;
-    double *Vmat = nullptr, *probe = nullptr, *Pm = nullptr, *Oc = nullptr, *Dm = nullptr;
-  };
-  static constexpr int N_LANES = 4;
-  Lane lane[N_LANES];
+  // Batched randomized SVDs of up to MAX_RB dense chi^2 x chi^2 operators (the four isometry
+  // Grams, the three squeezer cores) as one chain of launches: per-entry CholeskyQR flags
+  // (bflag), the scratch of the passes (Gqb: six roles x MAX_RB x MAX_W^2) and the core SVDs.
+  static constexpr int MAX_RB = 4;
+  int* bflag = nullptr;
+  double *Gqb = nullptr, *Rbb = nullptr, *RbTb = nullptr, *Uhb = nullptr, *Shb = nullptr;
+  double *Vhb = nullptr;
   // One RG state per temperature of the batch; the step runs them in turn through the shared
   // scratch, with phi, psi, flag, acc, lnc, spectra, xrec and ttr pointing at the selected one.
   struct State {
@@ -247,8 +239,6 @@ struct tatrg_handle {
     bool need_fallback = true;  // a CholeskyQR pass failed in this temperature's last step
   };
   std::vector<State> states;
-  hipEvent_t fork = nullptr;
-  bool lanes = false;
 };
 
 namespace {
@@ -414,26 +404,12 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->Usq = cv.take(n2 * c); h->Vsq = cv.take(n2 * c);
   h->Umat = cv.take(n2 * c); h->Vmat = cv.take(n2 * c);
   h->small = nullptr;
-  for (int z = 0; z < tatrg_handle::N_LANES; ++z) {
-    tatrg_handle::Lane& ln = h->lane[z];
-    ln.Pb = cv.take(n2 * L);
-    ln.P3 = cv.take(n2 * L);
-    ln.Gq = cv.take(6 * (int64_t)MAX_W * MAX_W);
-    ln.tsqr_ws = cv.take(tsqr_ws_doubles(n2, (int)L));
-    ln.partial_doubles = (size_t)(8 * n2 * L);
-    ln.partial = cv.take(ln.partial_doubles);
-    ln.flag = (int*)cv.take(8);
-    const int64_t ww = L;
-    ln.Pa = cv.take(n2 * ww);
-    ln.Cm = cv.take(n2 * n2);
-    ln.RbT = cv.take(ww * ww); ln.Rb = cv.take(ww * ww);
-    ln.Uh = cv.take(ww * ww); ln.Sh = cv.take(ww); ln.Vh = cv.take(ww * ww);
-    ln.Usq = cv.take(n2 * c); ln.Vsq = cv.take(n2 * c);
-    ln.Umat = cv.take(n2 * c); ln.Vmat = cv.take(n2 * c);
-    ln.probe = cv.take((int64_t)N_PROBES * n2);
-    ln.Pm = cv.take((int64_t)N_PROBES * ww);
-    ln.Oc = cv.take(ww * ww); ln.Dm = cv.take(ww);
-  }
+  // batched RSVDs (the pass-0 panels of orth_b go to P3, the panels themselves to P1, P2)
+  const int64_t rb = tatrg_handle::MAX_RB;
+  h->bflag = (int*)cv.take(8);
+  h->Gqb = cv.take(6 * rb * w * w);
+  h->Rbb = cv.take(rb * w * w); h->RbTb = cv.take(rb * w * w);
+  h->Uhb = cv.take(rb * w * w); h->Vhb = cv.take(rb * w * w); h->Shb = cv.take(rb * w);
 }
 
 bool hip_ok(tatrg_handle* h, const char* where) {
@@ -666,6 +642,95 @@ struct DenseOp : Op {
   }
 };
 
+// CholeskyQR3 of nb dense panels Y[e] (m x n, leading dimension n, stride sY, nb <= MAX_RB)
+// as one chain of batched launches, with per-panel flags (bflag) and the Householder fallback
+// per panel (the steps of orth).  R_out (stride sR) receives each R when given.
+void orth_b(tatrg_handle* h, double* Y, int64_t m, int n, int nb, int64_t sY, double* R_out,
+            int64_t sR) {
+  hipStream_t st = h->st;
+  int* fail = h->bflag;
+  const int64_t sq = (int64_t)MAX_W * MAX_W, rl = tatrg_handle::MAX_RB * sq, mn = m * n;
+  double* G1 = h->Gqb;
+  double* R0 = h->Gqb + rl;
+  double* R1 = h->Gqb + 2 * rl;
+  double* R2 = h->Gqb + 3 * rl;
+  double* Ri = h->Gqb + 4 * rl;
+  double* Rt = h->Gqb + 5 * rl;
+  const double shift = 11.0 * ((double)m * n + (double)n * (n + 1)) * 1.1102230246251565e-16;
+  zero((double*)fail, (nb + 1) / 2, st);
+  auto when_ok = [&](GemmArgs g) {
+    g.cond = fail;
+    g.cond_when = false;
+    g.cond_stride = 1;
+    return g;
+  };
+  int* sticky = h->speculate ? h->orth_sticky : nullptr;
+  // pass 0 (shifted)
+  gemm_long_k(h, Gb(G(n, n, m, Y, n, true, Y, n, false, G1, n), nb, sY, sY, sq));
+  chol_inv(G1, R0, Ri, n, 0, fail, st, shift, sticky, nb, sq, sq, sq, 1);
+  gemm(h, when_ok(Gb(G(m, n, n, Y, n, false, Ri, n, false, h->P3, n), nb, sY, sq, mn)));
+  // pass 1
+  gemm_long_k(h, when_ok(Gb(G(n, n, m, h->P3, n, true, h->P3, n, false, G1, n), nb, mn, mn,
+                            sq)));
+  chol_inv(G1, R1, Ri, n, 1, fail, st, 0.0, sticky, nb, sq, sq, sq, 1);
+  gemm(h, when_ok(Gb(G(m, n, n, h->P3, n, false, Ri, n, false, Y, n), nb, mn, sq, sY)));
+  // pass 2, in place (one tile column: every work-group reads only the rows it writes)
+  gemm_long_k(h, when_ok(Gb(G(n, n, m, Y, n, true, Y, n, false, G1, n), nb, sY, sY, sq)));
+  chol_inv(G1, R2, Ri, n, 2, fail, st, 0.0, sticky, nb, sq, sq, sq, 1);
+  gemm(h, when_ok(Gb(G(m, n, n, Y, n, false, Ri, n, false, Y, n), nb, sY, sq, sY)));
+  if (R_out) {  // success: R = R2 R1 R0
+    gemm(h, when_ok(Gb(G(n, n, n, R2, n, false, R1, n, false, Rt, n), nb, sq, sq, sq)));
+    gemm(h, when_ok(Gb(G(n, n, n, Rt, n, false, R0, n, false, R_out, n), nb, sq, sq, sR)));
+  }
+  if (h->speculate) return;  // see orth
+  for (int e = 0; e < nb; ++e) {
+    double* Ye = Y + e * sY;
+    hipLaunchKernelGGL(copy_panel_when_kernel, dim3(grid_for(mn)), dim3(TPB), 0, st,
+                       h->P3 + e * mn, (int64_t)n, Ye, (int64_t)n, m, n, fail + e, 2, 3);
+    tsqr(Ye, m, n, n, R_out ? Rt + e * sq : nullptr, h->tsqr_ws, st, fail + e);
+    if (R_out) {
+      GemmArgs a3 = G(n, n, n, Rt + e * sq, n, false, R0 + e * sq, n, false, R_out + e * sR, n);
+      a3.cond = fail + e;
+      a3.cond_when = true;
+      gemm(h, a3);
+      hipLaunchKernelGGL(copy_panel_when_kernel, dim3(grid_for((int64_t)n * n)), dim3(TPB), 0,
+                         st, Rt + e * sq, (int64_t)n, R_out + e * sR, (int64_t)n, (int64_t)n, n,
+                         fail + e, 1, 1);
+    }
+  }
+}
+
+// Randomized SVD of nb dense n x n operators M[e] (stride sM, nb <= MAX_RB) as one chain of
+// batched launches -- the steps of rsvd, with sketch site sites[e] for entry e.  Pa, Pb: nb
+// panels of n x w (stride n w); Pa ends as Q, Pb as Qb.  Unless range_only, the core SVDs of
+// Rb^T land in Uhb, Shb, Vhb (strides w^2, w).
+void rsvd_b(tatrg_handle* h, const double* M, int64_t sM, int nb, int64_t n, int w,
+            const uint32_t* sites, double* Pa, double* Pb, bool range_only) {
+  hipStream_t st = h->st;
+  const int64_t pw = n * w;
+  for (int e = 0; e < nb; ++e)
+    philox_gaussian(Pb + e * pw, n, w, w, false, h->cfg.seed, (uint32_t)h->step, sites[e], st);
+  auto apply = [&](const double* in, double* out) {
+    gemm_long_k(h, Gb(G(n, w, n, M, n, false, in, w, false, out, w), nb, sM, pw, pw));
+  };
+  auto apply_t = [&](const double* in, double* out) {
+    gemm_long_k(h, Gb(G(n, w, n, M, n, true, in, w, false, out, w), nb, sM, pw, pw));
+  };
+  apply(Pb, Pa);
+  orth_b(h, Pa, n, w, nb, pw, nullptr, 0);
+  for (int it = 0; it < h->cfg.q; ++it) {
+    apply_t(Pa, Pb);
+    orth_b(h, Pb, n, w, nb, pw, nullptr, 0);
+    apply(Pb, Pa);
+    orth_b(h, Pa, n, w, nb, pw, nullptr, 0);
+  }
+  if (range_only) return;
+  apply_t(Pa, Pb);
+  orth_b(h, Pb, n, w, nb, pw, h->Rbb, (int64_t)w * w);
+  transpose_batched(h->Rbb, h->RbTb, w, w, nb, st);
+  jacobi_svd(h->RbTb, h->Uhb, h->Shb, h->Vhb, w, nb, st);
+}
+
 // ---------------------------------------------------------------------------- step stages
 // S0: T = Phi Psi^T = A s B^T, gauge fixed, normalised.  rec: spectra slot or null.
 void canonicalize(tatrg_handle* h, int k, double* rec) {
@@ -862,35 +927,6 @@ void pair_gram(tatrg_handle* h, const double* T1, const double* T2, double* out)
   gemm_long_k(h, G(d.n2, d.n2, d.n3, h->Ap, d.n3, false, rhs, d.n3, true, out, d.n2));
 }
 
-// While alive, the handle's stream and per-task scratch are those of a lane, so the stage
-// functions enqueue onto it unchanged.
-struct LaneScope {
-  tatrg_handle* h;
-  tatrg_handle saved;  // the swapped fields of the handle (copied back on exit)
-  LaneScope(tatrg_handle* hh, const tatrg_handle::Lane& ln) : h(hh) {
-    saved.st = h->st; saved.P3 = h->P3; saved.Gq = h->Gq; saved.tsqr_ws = h->tsqr_ws;
-    saved.partial = h->partial; saved.partial_doubles = h->partial_doubles;
-    saved.flag = h->flag; saved.P1 = h->P1; saved.P2 = h->P2; saved.Cm = h->Cm;
-    saved.RbT = h->RbT; saved.Rb = h->Rb; saved.Uh = h->Uh; saved.Sh = h->Sh; saved.Vh = h->Vh;
-    saved.Usq = h->Usq; saved.Vsq = h->Vsq; saved.Umat = h->Umat; saved.Vmat = h->Vmat;
-    saved.probe = h->probe; saved.Pm = h->Pm; saved.Oc = h->Oc; saved.Dm = h->Dm;
-    h->st = ln.st; h->P3 = ln.P3; h->Gq = ln.Gq; h->tsqr_ws = ln.tsqr_ws;
-    h->partial = ln.partial; h->partial_doubles = ln.partial_doubles;
-    h->flag = ln.flag; h->P1 = ln.Pb; h->P2 = ln.Pa; h->Cm = ln.Cm;
-    h->RbT = ln.RbT; h->Rb = ln.Rb; h->Uh = ln.Uh; h->Sh = ln.Sh; h->Vh = ln.Vh;
-    h->Usq = ln.Usq; h->Vsq = ln.Vsq; h->Umat = ln.Umat; h->Vmat = ln.Vmat;
-    h->probe = ln.probe; h->Pm = ln.Pm; h->Oc = ln.Oc; h->Dm = ln.Dm;
-  }
-  ~LaneScope() {
-    h->st = saved.st; h->P3 = saved.P3; h->Gq = saved.Gq; h->tsqr_ws = saved.tsqr_ws;
-    h->partial = saved.partial; h->partial_doubles = saved.partial_doubles;
-    h->flag = saved.flag; h->P1 = saved.P1; h->P2 = saved.P2; h->Cm = saved.Cm;
-    h->RbT = saved.RbT; h->Rb = saved.Rb; h->Uh = saved.Uh; h->Sh = saved.Sh; h->Vh = saved.Vh;
-    h->Usq = saved.Usq; h->Vsq = saved.Vsq; h->Umat = saved.Umat; h->Vmat = saved.Vmat;
-    h->probe = saved.probe; h->Pm = saved.Pm; h->Oc = saved.Oc; h->Dm = saved.Dm;
-  }
-};
-
 void isometries(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
@@ -916,29 +952,9 @@ void isometries(tatrg_handle* h) {
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rY, n2));
   gemm(h, G(d.n4, c, c, h->B, c, false, py, c, false, h->AP, c));
   pair_gram(h, h->B, h->AP, rD);
-  // the four range finders are independent: one lane each (fork and join by events)
+  // the four range finders as one batched chain: U^Z lands in UZ + z n2 L
   const uint32_t sites[4] = {SITE_ISO_A, SITE_ISO_X, SITE_ISO_Y, SITE_ISO_D};
-  if (h->lanes) hipEventRecord(h->fork, st);
-  for (int z = 0; z < 4; ++z) {
-    DenseOp op;
-    op.h = h;
-    op.M = h->rho + z * n2 * n2;
-    op.n = n2;
-    double* U = h->UZ + z * n2 * d.L;
-    if (h->lanes) {
-      tatrg_handle::Lane& ln = h->lane[z];
-      hipStreamWaitEvent(ln.st, h->fork, 0);
-      {
-        LaneScope scope(h, ln);
-        rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, ln.Pb, true, true);
-      }
-      hipEventRecord(ln.done, ln.st);
-    } else {
-      rsvd(h, op, n2, n2, d.L, h->cfg.q, sites[z], U, h->P1, true, true);
-    }
-  }
-  if (h->lanes)
-    for (int z = 0; z < 4; ++z) hipStreamWaitEvent(st, h->lane[z].done, 0);
+  rsvd_b(h, h->rho, n2 * n2, 4, n2, d.L, sites, h->UZ, h->P1, true);
 }
 
 void triad(tatrg_handle* h) {
@@ -1016,53 +1032,45 @@ void squeezers(tatrg_handle* h, double* rec) {
   cholesky_shifted_inv(h->chol, h->sqdi, (int)n2, 6, CHOL_SHIFT, h->flag, st);
   const uint32_t sq_sites[3] = {SITE_SQZ_2, SITE_SQZ_3, SITE_SQZ_4};
   const uint32_t pr_sites[3] = {SITE_PROBE_SQZ_2, SITE_PROBE_SQZ_3, SITE_PROBE_SQZ_4};
-  // the three squeezer pairs are independent after the Cholesky factors: one lane each
-  if (h->lanes) hipEventRecord(h->fork, st);
+  // the three squeezer pairs after the shared Cholesky: C = R_L R_R^T = Ll^T Lr for each
+  // (rho_L + shift = Ll Ll^T, R_L = Ll^T; R_R = Lr^T), into the Grams' space, then one batched
+  // randomized SVD of the three (Q in P2, Qb in P1, cores in Uhb, Shb, Vhb)
+  const int w = d.L;
+  gemm(h, Gb(G(n2, n2, n2, h->chol, n2, true, h->chol + 3 * n2 * n2, n2, false, h->rho, n2), 3,
+             n2 * n2, n2 * n2, n2 * n2));
+  rsvd_b(h, h->rho, n2 * n2, 3, n2, w, sq_sites, h->P2, h->P1, false);
   for (int mi = 0; mi < 3; ++mi) {
-    if (h->lanes) hipStreamWaitEvent(h->lane[mi].st, h->fork, 0);
-    {
-      std::unique_ptr<LaneScope> scope;
-      if (h->lanes) scope.reset(new LaneScope(h, h->lane[mi]));
-      hipStream_t ls = h->st;
-      const double* Ll = h->chol + mi * n2 * n2;        // rho_L + shift = Ll Ll^T, R_L = Ll^T
-      const double* Lr = h->chol + (3 + mi) * n2 * n2;  // R_R = Lr^T
-      // C = R_L R_R^T = Ll^T Lr
-      gemm(h, G(n2, n2, n2, Ll, n2, true, Lr, n2, false, h->Cm, n2));
-      DenseOp op;
-      op.h = h;
-      op.M = h->Cm;
-      op.n = n2;
-      const int w = d.L;
-      rsvd(h, op, n2, n2, w, h->cfg.q, sq_sites[mi], h->P2, h->P1, false, true);
-      // U = Q Uh[:, :c], V = Qb Vh[:, :c]
-      gemm(h, G(n2, c, w, h->P2, w, false, h->Uh, w, false, h->Usq, c));
-      gemm(h, G(n2, c, w, h->P1, w, false, h->Vh, w, false, h->Vsq, c));
-      double* S = h->Ssq + mi * c;
-      hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, ls, S, h->Sh, (int)c);
-      if (rec)
-        hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, ls, rec + mi * c, h->Sh,
-                           (int)c);
-      philox_gaussian(h->probe, N_PROBES, n2, n2, false, h->cfg.seed, (uint32_t)h->step,
-                      pr_sites[mi], ls);
-      gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
-      gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, ls);
-      hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, ls, S, h->Dm, (int)c, SQZ_CUTOFF);
-      // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
-      // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
-      double* M = h->Msq + mi * n2 * c;
-      gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
-      scale_cols(h->Vmat, h->Dm, n2, c, c, ls);
-      gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
-      // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
-      gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
-      scale_cols(h->Umat, h->Dm, n2, c, c, ls);
-      gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
-      transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, ls);
-    }
-    if (h->lanes) hipEventRecord(h->lane[mi].done, h->lane[mi].st);
+    const double* Ll = h->chol + mi * n2 * n2;
+    const double* Lr = h->chol + (3 + mi) * n2 * n2;
+    const double* Q = h->P2 + mi * n2 * w;
+    const double* Qb = h->P1 + mi * n2 * w;
+    const double* Uh = h->Uhb + (int64_t)mi * w * w;
+    const double* Vh = h->Vhb + (int64_t)mi * w * w;
+    const double* Sh = h->Shb + mi * w;
+    // U = Q Uh[:, :c], V = Qb Vh[:, :c]
+    gemm(h, G(n2, c, w, Q, w, false, Uh, w, false, h->Usq, c));
+    gemm(h, G(n2, c, w, Qb, w, false, Vh, w, false, h->Vsq, c));
+    double* S = h->Ssq + mi * c;
+    hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, S, Sh, (int)c);
+    if (rec)
+      hipLaunchKernelGGL(copy_small_kernel, dim3(1), dim3(64), 0, st, rec + mi * c, Sh, (int)c);
+    philox_gaussian(h->probe, N_PROBES, n2, n2, false, h->cfg.seed, (uint32_t)h->step,
+                    pr_sites[mi], st);
+    gemm(h, G(N_PROBES, c, n2, h->probe, n2, false, h->Vsq, c, false, h->Pm, c));
+    gauge_rotation(S, h->Pm, h->Oc, (int)c, N_PROBES, TAU_NULL, TAU_DEG, st);
+    hipLaunchKernelGGL(mask_kernel, dim3(1), dim3(128), 0, st, S, h->Dm, (int)c, SQZ_CUTOFF);
+    // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
+    // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
+    double* M = h->Msq + mi * n2 * c;
+    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
+    scale_cols(h->Vmat, h->Dm, n2, c, c, st);
+    gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
+    // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
+    gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
+    scale_cols(h->Umat, h->Dm, n2, c, c, st);
+    gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
+    transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, st);
   }
-  if (h->lanes)
-    for (int mi = 0; mi < 3; ++mi) hipStreamWaitEvent(st, h->lane[mi].done, 0);
 }
 
 // One half of the contraction (Eqs. (makeMG) / (makeMH)):
@@ -1171,13 +1179,6 @@ tatrg_status tatrg_create(const tatrg_config* cfg, void* d_ws, size_t ws_bytes, 
   char* base = (char*)(((uintptr_t)d_ws + 255) & ~(uintptr_t)255);
   Carver cv{base};
   carve(h, cv);
-  // lane streams (default priority) and events; without them the stages run on `stream` alone
-  bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
-  for (int z = 0; ok && z < tatrg_handle::N_LANES; ++z) {
-    ok = hipStreamCreateWithFlags(&h->lane[z].st, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&h->lane[z].done, hipEventDisableTiming) == hipSuccess;
-  }
-  h->lanes = ok;
   (void)hipGetLastError();
   *out = h;
   return TATRG_OK;
@@ -1528,7 +1529,6 @@ tatrg_status tatrg_rsvd_noalloc(const double* d_A, int64_t m, int64_t n, int64_t
   tatrg_handle h;
   h.cfg = tatrg_config{};
   h.st = (hipStream_t)stream;
-  h.lanes = false;
   if (!carve_noalloc(&h, base, m, n, w)) return TATRG_EINVAL;
   return standalone_rsvd(&h, d_A, m, n, lda, k, w, q, seed, site, d_U, d_S, d_Vt);
 }
@@ -1835,14 +1835,6 @@ void tatrg_destroy(tatrg_handle* h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
   for (hipEvent_t e : h->sev) hipEventDestroy(e);
-  for (int z = 0; z < tatrg_handle::N_LANES; ++z) {
-    if (h->lane[z].st) {
-      hipStreamSynchronize(h->lane[z].st);
-      hipStreamDestroy(h->lane[z].st);
-    }
-    if (h->lane[z].done) hipEventDestroy(h->lane[z].done);
-  }
-  if (h->fork) hipEventDestroy(h->fork);
   delete h;
 }
 

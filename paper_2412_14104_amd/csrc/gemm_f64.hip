@@ -42,7 +42,9 @@ template <bool TA, bool TB, bool PLAIN, int TN>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
   constexpr int BNT = 32 * TN, EB = BNT * BK / NT;
   const GemmArgs& g = ka.g;
-  if (g.cond && ((*g.cond != 0) != g.cond_when)) return;
+  if (g.cond && ((g.cond[(int64_t)(blockIdx.z / ka.kparts) * g.cond_stride] != 0) !=
+                 g.cond_when))
+    return;
   // tile: blockIdx.(x, y) = (N tile, M tile); for a symmetric split-K product blockIdx.x
   // enumerates the tiles on and above the diagonal column by column, t = tn (tn + 1) / 2 + tm,
   // so consecutive work-groups (which the dispatcher spreads over the XCDs) share the load
@@ -188,12 +190,14 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
 // (i, j) of a tile below it is read from (j, i).
 __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64_t N,
                               int64_t ldc, int64_t sC, int kparts, int64_t batch, double alpha,
-                              double beta, const int* cond, int cond_when, int sym) {
-  if (cond && ((*cond != 0) != (cond_when != 0))) return;
+                              double beta, const int* cond, int cond_when, int sym,
+                              int64_t cond_stride) {
+  if (cond && cond_stride == 0 && ((*cond != 0) != (cond_when != 0))) return;
   const int64_t total = batch * M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = idx / (M * N);
+    if (cond && cond_stride > 0 && ((cond[b * cond_stride] != 0) != (cond_when != 0))) continue;
     const int64_t r = idx - b * M * N;
     const int64_t i = r / N, j = r - (r / N) * N;
     const int64_t src = (sym && i / BM > j / BN) ? j * N + i : r;
@@ -518,7 +522,7 @@ void gemm_f64_splitk(const GemmArgs& g, int parts, double* partial, hipStream_t 
   const int sym = (g.sym && g.M == g.N) ? 1 : 0;
   hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, partial, g.C,
                      g.M, g.N, g.ldc, g.sC, used, g.batch, g.alpha, g.beta, g.cond,
-                     g.cond_when ? 1 : 0, sym);
+                     g.cond_when ? 1 : 0, sym, g.cond_stride);
 }
 
 }  // namespace tatrg

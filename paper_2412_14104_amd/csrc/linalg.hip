@@ -602,21 +602,38 @@ __global__ void copy_if_kernel(double* y, const double* x, int64_t n, const int*
 // E[k][.]) to a double-buffered LDS vector; after one barrier every thread updates its rows
 // below k.  The step loop runs as an unrolled loop over the register slot of row k around a
 // loop over its group, so every register index is static.
-__global__ __launch_bounds__(1024) void chol_inv_kernel(const double* G, double* R, double* Ri,
-                                                         int n, int pass, int* fail,
-                                                         double shift_coef, int* sticky) {
+__global__ __launch_bounds__(1024) void chol_inv_kernel(const double* Gall, double* Rall,
+                                                         double* Riall, int n, int pass,
+                                                         int* fall, double shift_coef,
+                                                         int* sticky, int64_t sG, int64_t sR,
+                                                         int64_t sRi, int sf) {
   constexpr int RGP = 8, SL = 12;  // row groups and slots: 96 rows
   __shared__ double ra[2][128], re[2][128], dv[96];
+  __shared__ double red[2][2];
   __shared__ int bad;
   const int tid = threadIdx.x, q = tid & 127, g = tid >> 7;
+  const int64_t bi = blockIdx.x;  // batch entry
+  const double* G = Gall + bi * sG;
+  double* R = Rall + bi * sR;
+  double* Ri = Riall + bi * sRi;
+  int* fail = fall + bi * sf;
   if (*fail) return;  // uniform: read before any write of this launch
   double a[SL], e[SL];
-  double tr = 0.0, dmax = 0.0;
-  for (int k = 0; k < n; ++k) {  // diagonal of G: trace and largest entry (every thread)
-    const double dk = G[k * n + k];
-    tr += dk;
-    dmax = fmax(dmax, dk);
+  // diagonal of G: trace and largest entry, reduced over the first two waves
+  {
+    const double dk = (tid < n) ? G[tid * n + tid] : 0.0;
+    double sm = dk, mx = dk;
+    for (int o = 32; o > 0; o >>= 1) {
+      sm += __shfl_xor(sm, o, 64);
+      mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((tid & 63) == 0 && tid < 128) {
+      red[0][tid >> 6] = sm;
+      red[1][tid >> 6] = mx;
+    }
+    __syncthreads();
   }
+  const double tr = red[0][0] + red[0][1], dmax = fmax(red[1][0], red[1][1]);
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
     const int i = g + RGP * s;
@@ -1005,9 +1022,11 @@ void chol_check(const double* L, int n, int batch, double min_ratio, double lo, 
 }
 
 void chol_inv(const double* G, double* R, double* Rinv, int n, int pass, int* fail,
-              hipStream_t st, double shift_coef, int* sticky) {
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, R, Rinv, n, pass, fail,
-                     shift_coef, sticky);
+              hipStream_t st, double shift_coef, int* sticky, int batch, int64_t sG,
+              int64_t sR, int64_t sRi, int sf) {
+  if (batch < 1) return;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)batch), dim3(1024), 0, st, G, R, Rinv, n,
+                     pass, fail, shift_coef, sticky, sG, sR, sRi, sf);
 }
 
 void jacobi_svd(const double* A, double* U, double* S, double* V, int n, int batch,
