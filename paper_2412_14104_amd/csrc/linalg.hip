@@ -619,6 +619,12 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* Gall, doub
   int* fail = fall + bi * sf;
   if (*fail) return;  // uniform: read before any write of this launch
   double a[SL], e[SL];
+  // the published row entries of columns q >= n stay zero (so are the multipliers of padding
+  // rows and the updates of padding columns)
+  if (g == 0 && q >= n) {
+    ra[0][q] = ra[1][q] = 0.0;
+    re[0][q] = re[1][q] = 0.0;
+  }
   // diagonal of G: trace and largest entry, reduced over the first two waves
   {
     const double dk = (tid < n) ? G[tid * n + tid] : 0.0;
@@ -663,16 +669,20 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(const double* Gall, doub
         dv[k] = d;
       }
       const double rd = 1.0 / (ok ? d : 1.0);
-      if (q < n) {
-        const double akq = ra[bf][q], ekq = re[bf][q];
+      // rows i > k below the pivot: a -= m_i A[k][.], e -= m_i E[k][.] without a per-column
+      // condition.  A's entries left of the diagonal (q < i) are never read back, E[k][q] is
+      // zero for q > k, and the multipliers of padding rows (i >= n) are zero; the
+      // multipliers are read from LDS in one batch before the updates.
+      const double akq = ra[bf][q], ekq = re[bf][q];
+      double mrow[SL];
 #pragma unroll
-        for (int s = kk; s < SL; ++s) {
-          const int i = g + RGP * s;
-          if (i <= k || i >= n) continue;
-          const double mi = ra[bf][i] * rd;
-          if (q >= i) a[s] -= mi * akq;
-          else if (q <= k) e[s] -= mi * ekq;
-        }
+      for (int s = kk; s < SL; ++s) mrow[s] = ra[bf][g + RGP * s];
+#pragma unroll
+      for (int s = kk; s < SL; ++s) {
+        if (s == kk && g <= kg) continue;  // rows i <= k are final (wave-uniform)
+        const double mi = mrow[s] * rd;
+        a[s] -= mi * akq;
+        e[s] -= mi * ekq;
       }
     }
   }
@@ -842,6 +852,10 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double*
 #pragma unroll
   for (int c = 0; c < 64; ++c) row[c] = (r < jb && c < jb) ? blk[r][c] : 0.0;
   __syncthreads();
+  // Column k: every lane scales and publishes its entry, then updates its whole row to the
+  // right of k without a per-lane condition: entries above the diagonal (c > r) take values
+  // that are never read back, and padding rows (r >= jb) hold zeros throughout.  The
+  // multipliers of the row are read from LDS in one batch before the updates.
 #pragma unroll
   for (int k = 0; k < 64; ++k) {
     if (k < jb) {
@@ -852,9 +866,11 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double*
       if (r > k) row[k] /= dk;
       lk[r] = row[k];
       __syncthreads();
+      double l[64];
 #pragma unroll
-      for (int c = k + 1; c < 64; ++c)
-        if (c <= r && r < jb) row[c] -= row[k] * lk[c];
+      for (int c = k + 1; c < 64; ++c) l[c] = lk[c];
+#pragma unroll
+      for (int c = k + 1; c < 64; ++c) row[c] -= row[k] * l[c];
       __syncthreads();
     }
   }
@@ -864,16 +880,24 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double*
   __syncthreads();
   for (int rr = 0; rr < jb; ++rr)
     if (r < jb) A[(int64_t)(j + rr) * n + j + r] = blk[rr][r];
-  // column r of L_jj^{-1}: x_i = (delta_ir - sum_{r <= k < i} L_ik x_k) / L_ii, i >= r
+  // column r of L_jj^{-1}: x_i = (delta_ir - sum_{k < i} L_ik x_k) / L_ii, which is zero for
+  // i < r without a condition (x_k = 0 for k < r); four partial sums shorten the chain
   double x[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
     double v = 0.0;
-    if (i < jb && i >= r) {
-      v = (i == r) ? 1.0 : 0.0;
+    if (i < jb) {
+      double p0 = (i == r) ? 1.0 : 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-      for (int k = 0; k < i; ++k) v -= blk[i][k] * x[k];
-      v /= blk[i][i];
+      for (int k = 0; k + 3 < i; k += 4) {
+        p0 -= blk[i][k] * x[k];
+        p1 -= blk[i][k + 1] * x[k + 1];
+        p2 -= blk[i][k + 2] * x[k + 2];
+        p3 -= blk[i][k + 3] * x[k + 3];
+      }
+#pragma unroll
+      for (int k = i & ~3; k < i; ++k) p0 -= blk[i][k] * x[k];
+      v = ((p0 + p1) + (p2 + p3)) / blk[i][i];
     }
     x[i] = v;
   }

@@ -15,6 +15,7 @@ ordered (X = 2) fixed points, by linear interpolation between neighbouring tempe
 """
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -89,9 +90,12 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--preset", default="C4")
     ap.add_argument("--precision", choices=["fp64", "bf16x3"], default="fp64")
-    ap.add_argument("--engines", type=int, default=4,
+    ap.add_argument("--engines", type=int, default=8,
                     help="handles (streams, host threads) the temperatures are dealt to")
     args = ap.parse_args(argv)
+    # one hardware queue per handle's stream (HIP's default is 4 per process); read when the
+    # runtime starts, so it is set before torch initialises the device
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(max(args.engines, 4), 16)))
 
     import torch
     if not torch.cuda.is_available():
