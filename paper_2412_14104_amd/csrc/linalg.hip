@@ -22,6 +22,26 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// v from another lane of the same 16-lane row by a DPP move (CTRL: a quad permutation or a
+// row mirror), both 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a row, the same value in every lane: pairs (quad permutation
+// [1,0,3,2]), quads ([2,3,0,1]), then the two quads of each half row (half-row mirror) and the
+// two halves (row mirror) -- the grouping of a butterfly over lane masks 1, 2, 4, 8.
+__device__ inline double row16_sum(double v) {
+  v += dpp_double<0xB1>(v);
+  v += dpp_double<0x4E>(v);
+  v += dpp_double<0x141>(v);
+  v += dpp_double<0x140>(v);
+  return v;
+}
+
 // ------------------------------------------------------------------------------ TSQR
 // Householder QR of row blocks with the panel held in registers: thread t owns column
 // c = t % CW and the rows i = g + RG k (g = t / CW < RG, k < RPG) of its block, so the rank-1
@@ -368,12 +388,9 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
           bb += yr[t] * yr[t];
           g += xr[t] * yr[t];
         }
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-          a += __shfl_xor(a, o, 64);
-          bb += __shfl_xor(bb, o, 64);
-          g += __shfl_xor(g, o, 64);
-        }
+        a = row16_sum(a);
+        bb = row16_sum(bb);
+        g = row16_sum(g);
         if (a > 0.0 && bb > 0.0 && fabs(g) > tol * sqrt(a * bb)) {
           const double zeta = (bb - a) / (2.0 * g);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -388,10 +405,20 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
           }
           double* vp = V + (size_t)p * ne;
           double* vq = V + (size_t)q * ne;
-          for (int i = sub; i < ne; i += 16) {
-            const double x = vp[i], y = vq[i];
-            vp[i] = c * x - s * y;
-            vq[i] = s * x + c * y;
+          double xv[6], yv[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            const int i = sub + 16 * t;
+            xv[t] = (i < ne) ? vp[i] : 0.0;
+            yv[t] = (i < ne) ? vq[i] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            const int i = sub + 16 * t;
+            if (i < ne) {
+              vp[i] = c * xv[t] - s * yv[t];
+              vq[i] = s * xv[t] + c * yv[t];
+            }
           }
           if (sub == 0) rotated = 1;
         }
