@@ -171,6 +171,13 @@ void permute(const double* in, double* out, int rank, const int64_t* dims, const
 void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t ld,
                 hipStream_t st);
 
+// A factor L (n x n) with L L^T = P of `batch` symmetric positive semidefinite P (n <= 96,
+// strides n^2): the Jacobi SVD P = U S V^T, L = U S^{1/2} (U = V on the nonzero singular
+// values of a semidefinite P; columns with S = 0 are zero).  S, V: scratch of batch n and
+// batch n^2 doubles.
+void psd_factor(const double* P, double* L, double* S, double* V, int n, int batch,
+                hipStream_t st);
+
 // y = x (n doubles).
 // Order parameter X = (Tr A)^2 / Tr A^2 of T = sum_g Phi[., g] Psi[., g] (chi^5 doubles
 // each, legs (l1 l2 l3 l4 gamma)), A_kl = T with the legs of the three slots other than

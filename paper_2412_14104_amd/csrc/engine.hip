@@ -171,7 +171,7 @@ struct tatrg_handle {
   // buffers
   double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
   double *Xs, *Ys, *AP, *Ap, *APp, *rho, *UZ, *E, *F, *Gt, *H;
-  double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm2, *pm3, *sq1, *sq2, *sq3, *sq4;
+  double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm3, *sq1, *sq2, *sq3, *sq4;
   double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
   double *partial, *probe, *small, *planes;
   // compressed cell middle of the bond swap: the two panels [f'][(x beta)], [b'][(x alpha)]
@@ -358,7 +358,7 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->E = cv.take(L * n3); h->F = cv.take(L * n3); h->Gt = cv.take(L * n3); h->H = cv.take(L * n3);
   h->Ah = cv.take(n5); h->Xh = cv.take(n5); h->Yh = cv.take(n5); h->Dh = cv.take(n5);
   h->XA = cv.take(n5); h->xg = cv.take(n5); h->yg = cv.take(n5);
-  h->pm1 = cv.take(n5); h->pm2 = cv.take(n5); h->pm3 = cv.take(n5);
+  h->pm1 = cv.take(n5); h->pm3 = cv.take(n5);
   h->sq1 = cv.take(n2 * n2); h->sq2 = cv.take(n2 * n2); h->sq3 = cv.take(n2 * n2);
   h->sq4 = cv.take(n2 * n2);
   h->chol = cv.take(6 * n2 * n2);
@@ -935,23 +935,29 @@ void isometries(tatrg_handle* h) {
   scale_cols(h->Xs, h->sig, d.n4, c, c, st);
   copy(h->Ys, h->Y, d.n5, st);
   scale_cols(h->Ys, h->sig, d.n4, c, c, st);
-  double* px = h->Cc;
-  double* py = h->Uc;
+  // P_X = (X sigma)(X sigma)^T and P_Y alike (c x c, semidefinite), side by side in the
+  // batched scratch, and factors L L^T = P: rho_A = sum A P_X A^T = (A L_X)(A L_X)^T is then a
+  // symmetric Gram (half the tiles of the product), and rho_D alike
+  double* px = h->Gqb;
+  double* py = h->Gqb + c * c;
+  double* lx = h->Uhb;
+  double* ly = h->Uhb + c * c;
   gemm_long_k(h, G(c, c, d.n4, h->Xs, d.n4, false, h->Xs, d.n4, true, px, c));
   gemm_long_k(h, G(c, c, d.n4, h->Ys, d.n4, false, h->Ys, d.n4, true, py, c));
+  psd_factor(px, lx, h->Shb, h->Vhb, (int)c, 2, st);
   double* rA = h->rho;
   double* rX = h->rho + n2 * n2;
   double* rY = h->rho + 2 * n2 * n2;
   double* rD = h->rho + 3 * n2 * n2;
-  gemm(h, G(d.n4, c, c, h->A, c, false, px, c, false, h->AP, c));
-  pair_gram(h, h->A, h->AP, rA);
+  gemm(h, G(d.n4, c, c, h->A, c, false, lx, c, false, h->AP, c));
+  pair_gram(h, h->AP, h->AP, rA);
   // X-type: [alpha, f2, f3, f4, g] -> [(f2 f3), alpha, f4, g]
   perm(h, h->Xs, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rX, n2));
   perm(h, h->Ys, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rY, n2));
-  gemm(h, G(d.n4, c, c, h->B, c, false, py, c, false, h->AP, c));
-  pair_gram(h, h->B, h->AP, rD);
+  gemm(h, G(d.n4, c, c, h->B, c, false, ly, c, false, h->AP, c));
+  pair_gram(h, h->AP, h->AP, rD);
   // the four range finders as one batched chain: U^Z lands in UZ + z n2 L
   const uint32_t sites[4] = {SITE_ISO_A, SITE_ISO_X, SITE_ISO_Y, SITE_ISO_D};
   rsvd_b(h, h->rho, n2 * n2, 4, n2, d.L, sites, h->UZ, h->P1, true);
@@ -987,17 +993,24 @@ void squeezers(tatrg_handle* h, double* rec) {
   gemm(h, Gb(G(n2, n2, L, UD, L, false, h->H, n2, false, h->Dh, n2), c, 0, L * n2, n4));
   double* aag = h->Cc;
   double* ddg = h->Uc;
-  double* gf = h->Vc;
-  double* gb = h->Rp;
+  // g_f, g_b side by side in the batched scratch, their factors L L^T = g in Uhb
+  double* gf = h->Gqb;
+  double* gb = h->Gqb + c * c;
+  double* lf = h->Uhb;
+  double* lb = h->Uhb + c * c;
   gemm_long_k(h, G(c, c, n4, h->Ah, c, true, h->Ah, c, false, aag, c));
   gemm_long_k(h, G(c, c, n4, h->Dh, c, true, h->Dh, c, false, ddg, c));
-  // g_f = Xh^T (aag^T Xh), g_b = Yh^T (ddg^T Yh) with Xh viewed (c x n4) / (n4 x c)
+  // g_f = Xh^T (aag^T Xh), g_b = Yh^T (ddg^T Yh) with Xh viewed (c x n4) / (n4 x c): Grams of
+  // Ah Xh and Dh Yh, so semidefinite
   gemm(h, G(c, n4, c, aag, c, true, h->Xh, n4, false, h->XA, n4));
   gemm_long_k(h, G(c, c, n4, h->Xh, c, true, h->XA, c, false, gf, c));
   gemm(h, G(c, n4, c, ddg, c, true, h->Yh, n4, false, h->XA, n4));
   gemm_long_k(h, G(c, c, n4, h->Yh, c, true, h->XA, c, false, gb, c));
-  gemm(h, G(n4, c, c, h->Xh, c, false, gb, c, false, h->xg, c));
-  gemm(h, G(n4, c, c, h->Yh, c, false, gf, c, false, h->yg, c));
+  psd_factor(gf, lf, h->Shb, h->Vhb, (int)c, 2, st);
+  // xg = Xh L_b, yg = Yh L_f: the Grams of the forward and backward pairs below are then
+  // symmetric products of one operand (sum Xh g_b Xh^T = (Xh L_b)(Xh L_b)^T)
+  gemm(h, G(n4, c, c, h->Xh, c, false, lb, c, false, h->xg, c));
+  gemm(h, G(n4, c, c, h->Yh, c, false, lf, c, false, h->yg, c));
 
   const std::vector<int> a_perm[3] = {{1, 4, 0, 2, 3}, {2, 4, 0, 1, 3}, {3, 4, 0, 1, 2}};
   const std::vector<int> x_perm[3] = {{0, 1, 2, 3, 4}, {0, 2, 1, 3, 4}, {0, 3, 1, 2, 4}};
@@ -1009,17 +1022,15 @@ void squeezers(tatrg_handle* h, double* rec) {
     // rho_L = sum_{a a'} aa[u1 a u1' a'] xx[a u2 a' u2']
     perm(h, h->Ah, h->pm1, d5, a_perm[mi]);
     gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
-    perm(h, h->Xh, h->pm2, d5, x_perm[mi]);
     perm(h, h->xg, h->pm3, d5, x_perm[mi]);
-    gemm_long_k(h, G(n2, n2, n3, h->pm2, n3, false, h->pm3, n3, true, h->sq2, n2));
+    gemm_long_k(h, G(n2, n2, n3, h->pm3, n3, false, h->pm3, n3, true, h->sq2, n2));
     perm(h, h->sq1, h->sq3, d4, {0, 2, 1, 3});
     perm(h, h->sq2, h->sq4, d4, {0, 2, 1, 3});
     gemm(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
     perm(h, h->sq1, rl, d4, {0, 2, 1, 3});
     // rho_R = sum_{b b'} yy[b v1 b' v1'] dd[v2 b v2' b']
-    perm(h, h->Yh, h->pm2, d5, x_perm[mi]);
     perm(h, h->yg, h->pm3, d5, x_perm[mi]);
-    gemm_long_k(h, G(n2, n2, n3, h->pm2, n3, false, h->pm3, n3, true, h->sq2, n2));
+    gemm_long_k(h, G(n2, n2, n3, h->pm3, n3, false, h->pm3, n3, true, h->sq2, n2));
     perm(h, h->Dh, h->pm1, d5, a_perm[mi]);
     gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
     perm(h, h->sq2, h->sq3, d4, {1, 3, 0, 2});

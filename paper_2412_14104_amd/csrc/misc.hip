@@ -186,6 +186,17 @@ __global__ void scale_cols_kernel(double* x, const double* s, int64_t rows, int6
   }
 }
 
+// U[b] <- U[b] diag(sqrt(S[b])) for `batch` n x n matrices (strides n^2 and n).
+__global__ void sqrt_scale_cols_kernel(double* U, const double* S, int n, int batch) {
+  const int64_t total = (int64_t)batch * n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / ((int64_t)n * n);
+    const int j = (int)(idx % n);
+    U[idx] *= sqrt(S[b * n + j]);
+  }
+}
+
 __global__ void copy_kernel(double* y, const double* x, int64_t n) {
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x)
@@ -386,6 +397,14 @@ void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t 
                 hipStream_t st) {
   hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(rows * cols)), dim3(TPB), 0, st, x, s,
                      rows, cols, ld);
+}
+
+void psd_factor(const double* P, double* L, double* S, double* V, int n, int batch,
+                hipStream_t st) {
+  jacobi_svd(P, L, S, V, n, batch, st);
+  const int64_t total = (int64_t)batch * n * n;
+  hipLaunchKernelGGL(sqrt_scale_cols_kernel, dim3(grid_for(total)), dim3(TPB), 0, st, L, S, n,
+                     batch);
 }
 
 void copy(double* y, const double* x, int64_t n, hipStream_t st) {
