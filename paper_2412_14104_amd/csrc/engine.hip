@@ -381,7 +381,11 @@ void carve(tatrg_handle* h, Carver& cv) {
     GemmArgs g1 = G(c * L, L * n2, n2, nullptr, n2, false, nullptr, L * n2, false, nullptr, 0);
     GemmArgs g2 = Gb(G(n2, n2, L * L, nullptr, n2, true, nullptr, n2, false, nullptr, 0), c, 0,
                      L * L * n2, n4);
-    h->planes_doubles = std::max(gemm_bf16x3_ws_doubles(g1), gemm_bf16x3_ws_doubles(g2, true));
+    // and the swap's sketch map (Q1B^T Omega)
+    GemmArgs g3 = G(n2, c * d.Ls, n3, nullptr, n2, true, nullptr, c * d.Ls, false, nullptr, 0);
+    h->planes_doubles = std::max(std::max(gemm_bf16x3_ws_doubles(g1),
+                                          gemm_bf16x3_ws_doubles(g2, true)),
+                                 gemm_bf16x3_ws_doubles(g3));
     h->planes = cv.take(h->planes_doubles);
   }
   h->partial_doubles = splitk_partial_doubles(d);
@@ -873,7 +877,18 @@ bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
     // (Q_B x 1)^T Omega = L2B^{-1} Q1B^T Omega: rows (p', beta)
     philox_gaussian(h->P2, d.n4, w, w, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
                     d.n3);
-    gemm_long_k(h, G(d.n2, c * w, d.n3, Q1B, d.n2, true, h->P2, c * w, false, h->t1, c * w));
+    const GemmArgs gs = G(d.n2, c * w, d.n3, Q1B, d.n2, true, h->P2, c * w, false, h->t1, c * w);
+    // on the split path the sketch map (2 chi^6 Ls flops, the largest product of the compressed
+    // swap) runs on the split-bf16 engine: it only maps a Gaussian sketch, whose rounding at
+    // 2^-24 moves the randomized SVD's result far below the split path's error
+    if (h->cfg.precision == TATRG_BF16X3) {
+      if (!gemm_bf16x3(gs, h->planes, h->planes_doubles, st)) {
+        h->err = "split-bf16 plane workspace too small for the swap sketch map";
+        h->host_fault = true;
+      }
+    } else {
+      gemm_long_k(h, gs);
+    }
     gemm(h, G(d.n2, c * w, d.n2, L2iB, d.n2, false, h->t1, c * w, false, h->P1, c * w));
     op.fa = h->cra;               // R_A
     op.na = d.n2;
