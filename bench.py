@@ -135,6 +135,9 @@ def run_path(pkg, torch, precision, chi, r, q, seed, beta, warmup, steps, finish
     eng = pkg.Engine(chi, r, q, n_total, seed=seed, precision=precision, record_spectra=False)
     st = eng.stream
     eng.init(beta)
+    # measured work-group order of the split GEMMs (results do not depend on it); before the
+    # warm-up, outside the timed region
+    tuned = eng.autotune()
     for _ in range(warmup):
         eng.step()
     torch.cuda.synchronize()
@@ -163,7 +166,8 @@ def run_path(pkg, torch, precision, chi, r, q, seed, beta, warmup, steps, finish
            "contraction_ms": k_ms, "launches": launches, "flops_per_launch": flops_launch,
            "stage_ms_per_step": [x / max(stage_steps, 1) for x in stage_ms],
            "n_total": n_total, "f": f, "lnZV": lnzv,
-           "swap_compressed_timed_steps": sum(1 for p in swap_paths[warmup:] if p == 1)}
+           "swap_compressed_timed_steps": sum(1 for p in swap_paths[warmup:] if p == 1),
+           "autotune": tuned}
     del eng
     return out
 
@@ -285,6 +289,7 @@ def main():
         "roofline": roofline,
         "roofline_fp64_stages": roofline_fp64,
         "swap_compressed_timed_steps": main_run["swap_compressed_timed_steps"],
+        "split_gemm_grouping": main_run["autotune"],
         "stages": stage_report,
         "step_model_flops": total_flops,
         "step_model_tflops": total_flops * main_run["value"] / 1e12,

@@ -155,6 +155,17 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
 tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1,
                                    double* h_d2);
 
+/* Synchronising; between steps.  A measured table for the split-bf16 GEMMs of the step (the
+ * contraction of Eqs. (makeMG)/(makeMH): P = E.FM4 and Phi = Qt^T.P, and the bond swap's
+ * sketch map, Eq. (1)): each is timed at its real shape on the handle's scratch for
+ * work-group orders grouping 0, 2, 4, 6, 8 or 12 rows of tiles (which of the tiles run
+ * together, and so share operand tiles in an XCD's L2), and the fastest is kept for the
+ * following steps.  The order does not change any result: runs are bit for bit those without
+ * tuning.  No RG state is touched.  h_choice (host, 3 ints, may be NULL) receives the chosen
+ * groupings of the three GEMMs in that order (-1 each on the FP64 path, where the call does
+ * nothing).  EHIP on a HIP error, the defaults then stay in use. */
+tatrg_status tatrg_autotune(tatrg_handle* h, int32_t* h_choice);
+
 /* Synchronising.  Per-step records of temperature b (0 <= b < batch), kept when
  * record_spectra != 0, for step = 0..n_steps (step n_steps is recorded by
  * tatrg_free_energy):

@@ -98,6 +98,13 @@ int tatrg_test_cholesky_blocked_inv(double* A, double* Dinv, double* Linv, doubl
 int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pass,
                         double shift_coef, int* fail, void* stream);
 
+/* tatrg_test_chol_inv over `batch` Grams at once (G, R, Rinv: batch x n x n, contiguous), as
+ * the batched range finders run it: entry b has its own flag fail[b] (device ints), and a
+ * failed entry leaves the others unaffected.  Returns 0, -1 for bad arguments, -3 for a
+ * launch error. */
+int tatrg_test_chol_inv_batched(const double* G, double* R, double* Rinv, int n, int pass,
+                                double shift_coef, int* fail, int batch, void* stream);
+
 /* Gaussian sketch: element (i, j) of a rows x cols matrix is Philox4x32-10 draw number
  * i*cols + j of (seed, step, site). */
 int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,

@@ -61,6 +61,7 @@ _SIGS = {
     "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
     "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
     "tatrg_lnz_derivatives": (ctypes.c_int, [_p, _dblp, _dblp, _dblp]),
+    "tatrg_autotune": (ctypes.c_int, [_p, ctypes.POINTER(_i32)]),
     "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),
     "tatrg_get_record": (ctypes.c_int, [_p, _i32, _i32, _i32, _dblp, _i32,
                                         ctypes.POINTER(_i32)]),
@@ -89,6 +90,8 @@ _SIGS = {
                                                        ctypes.c_int, _p, _p]),
     "tatrg_test_chol_inv": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl, _p,
                                             _p]),
+    "tatrg_test_chol_inv_batched": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, ctypes.c_int, _dbl,
+                                                   _p, ctypes.c_int, _p]),
     "tatrg_test_philox": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),
     "tatrg_test_philox_words": (ctypes.c_int, [_p, _i64, _i64, _u64, _u32, _u32, _p]),
     "tatrg_test_permute": (ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.POINTER(_i64),
@@ -168,6 +171,13 @@ class Engine:
         if self.batch == 1:
             return f[0], lnzv[0]
         return list(f), list(lnzv)
+
+    def autotune(self):
+        """Measured work-group grouping of the split GEMMs (tatrg_autotune): the three
+        chosen values, or -1 each on the FP64 path."""
+        out = (_i32 * 3)()
+        _check(lib.tatrg_autotune(self.handle, out), self.handle)
+        return list(out)
 
     def lnz_derivatives(self):
         """For a batch of triples (beta - d, beta, beta + d): lists (ln Z/V, d(ln Z/V)/d beta,

@@ -54,9 +54,12 @@ struct Bf16PlanesOut {
 // R2 C2 <= Kp and every offset below cap).  Returns false, launching nothing, when
 // planes_ws holds fewer than gemm_bf16x3_ws_doubles(g, b_in != nullptr) doubles or an
 // argument of b_in or c_out does not fit.
+// group_m: rows of tiles per group of the work-group order (results do not depend on it);
+// -1 takes the default (6 with 12 or more rows of tiles, else 0: M fastest throughout).
 bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
                  hipStream_t st, hipEvent_t ev_after_split = nullptr,
-                 const Bf16PlanesIn* b_in = nullptr, const Bf16PlanesOut* c_out = nullptr);
+                 const Bf16PlanesIn* b_in = nullptr, const Bf16PlanesOut* c_out = nullptr,
+                 int group_m = -1);
 // Workspace (in doubles) gemm_bf16x3 needs for the bf16 planes it splits (op(A) always,
 // op(B) unless it is given as planes).
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given = false);

@@ -167,6 +167,9 @@ struct tatrg_handle {
   bool host_fault = false;  // a stage could not be enqueued (reported by tatrg_step)
   int64_t replays = 0;      // steps replayed after a speculation on the CholeskyQR passes failed
   bool force_speculation = false;  // testing: speculate on every step
+  // work-group grouping of the split GEMMs chosen by tatrg_autotune (-1: the default rule):
+  // [0] P = E.FM4, [1] Phi = Qt^T.P, [2] the swap's sketch map
+  int tuned_group[3] = {-1, -1, -1};
   std::vector<double> betas;
   // buffers
   double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
@@ -431,11 +434,11 @@ void gemm(tatrg_handle* h, const GemmArgs& g) { gemm_f64(g, h->st); }
 // bracket starts after the plane splitting, so it times the GEMM kernel alone).  b_in and
 // c_out (split path only) pass op(B) and C as bf16 planes.
 void gemm_timed(tatrg_handle* h, const GemmArgs& g, const Bf16PlanesIn* b_in = nullptr,
-                const Bf16PlanesOut* c_out = nullptr) {
+                const Bf16PlanesOut* c_out = nullptr, int group_m = -1) {
   const bool on = h->profile && h->ev_used + 2 <= (int)h->ev.size();
   hipEvent_t e0 = on ? h->ev[h->ev_used] : nullptr;
   if (h->cfg.precision == TATRG_BF16X3) {
-    if (!gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0, b_in, c_out)) {
+    if (!gemm_bf16x3(g, h->planes, h->planes_doubles, h->st, e0, b_in, c_out, group_m)) {
       h->err = "split-bf16 plane workspace too small for a contraction GEMM";
       h->host_fault = true;
     }
@@ -882,7 +885,8 @@ bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
     // swap) runs on the split-bf16 engine: it only maps a Gaussian sketch, whose rounding at
     // 2^-24 moves the randomized SVD's result far below the split path's error
     if (h->cfg.precision == TATRG_BF16X3) {
-      if (!gemm_bf16x3(gs, h->planes, h->planes_doubles, st)) {
+      if (!gemm_bf16x3(gs, h->planes, h->planes_doubles, st, nullptr, nullptr, nullptr,
+                       h->tuned_group[2])) {
         h->err = "split-bf16 plane workspace too small for the swap sketch map";
         h->host_fault = true;
       }
@@ -1122,7 +1126,7 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
     perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 4, 1, 3});
     const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, L, n2, L, Kp, 0, pn};
     gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, nullptr, 0),
-               nullptr, &po);
+               nullptr, &po, h->tuned_group[0]);
   } else {
     // FM4[i4a][a][kX][g][k4]
     perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
@@ -1139,7 +1143,7 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   if (split) {
     const Bf16PlanesIn pi = {{pp, pp + pn, pp + 2 * pn}, n2 * Kp};
     gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, nullptr, 0, false, h->phin, n2), c, 0,
-                     0, d.n4), &pi, nullptr);
+                     0, d.n4), &pi, nullptr, h->tuned_group[1]);
   } else {
     gemm_timed(h, Gb(G(n2, n2, L * L, h->Qt, n2, true, h->P, n2, false, h->phin, n2), c, 0,
                      L * L * n2, d.n4));
@@ -1710,6 +1714,78 @@ tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1
     if (h_d2) h_d2[i] = 2.0 * ((lp - l0) / (bp - b0) - (l0 - lm) / (b0 - bm)) / (bp - bm);
   }
   return s;
+}
+
+tatrg_status tatrg_autotune(tatrg_handle* h, int32_t* h_choice) {
+  if (!h) return TATRG_EINVAL;
+  if (h->cfg.precision != TATRG_BF16X3) {
+    if (h_choice)
+      for (int t = 0; t < 3; ++t) h_choice[t] = -1;
+    return TATRG_OK;
+  }
+  if (!settle(h)) {
+    h->err = "verification of the last step failed";
+    return TATRG_EHIP;
+  }
+  // the three split GEMMs of a step at their real shapes, on the handle's scratch (their
+  // inputs' values do not matter for the timing; no RG state is touched)
+  const Dims& d = h->d;
+  const int64_t c = d.c, n2 = d.n2, n3 = d.n3, L = d.L, w = d.Ls;
+  const int64_t Kp = bf16x3_kpad(L * L), pn = c * n2 * Kp;
+  uint16_t* pp = reinterpret_cast<uint16_t*>(h->P);
+  const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, L, n2, L, Kp, 0, pn};
+  const Bf16PlanesIn pi = {{pp, pp + pn, pp + 2 * pn}, n2 * Kp};
+  const GemmArgs gP = G(c * L, L * n2, n2, h->E, n2, false, h->FM4, L * n2, false, nullptr, 0);
+  const GemmArgs gPhi =
+      Gb(G(n2, n2, L * L, h->Qt, n2, true, nullptr, 0, false, h->phin, n2), c, 0, 0, d.n4);
+  const GemmArgs gS = G(n2, c * w, n3, h->cp, n2, true, h->P2, c * w, false, h->t1, c * w);
+  const int cand[6] = {0, 2, 4, 6, 8, 12};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    h->err = "autotune: event creation failed";
+    return TATRG_EHIP;
+  }
+  bool ok = true;
+  for (int t = 0; t < 3 && ok; ++t) {
+    float best = 0.0f;
+    int best_g = -1;
+    for (int ci = 0; ci < 6 && ok; ++ci) {
+      auto run = [&]() {
+        if (t == 0)
+          ok = ok && gemm_bf16x3(gP, h->planes, h->planes_doubles, h->st, nullptr, nullptr, &po,
+                                 cand[ci]);
+        else if (t == 1)
+          ok = ok && gemm_bf16x3(gPhi, h->planes, h->planes_doubles, h->st, nullptr, &pi,
+                                 nullptr, cand[ci]);
+        else
+          ok = ok && gemm_bf16x3(gS, h->planes, h->planes_doubles, h->st, nullptr, nullptr,
+                                 nullptr, cand[ci]);
+      };
+      run();  // warm-up
+      hipEventRecord(e0, h->st);
+      run();
+      run();
+      hipEventRecord(e1, h->st);
+      float ms = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        ok = false;
+      if (ok && (best_g < 0 || ms < best)) {
+        best = ms;
+        best_g = cand[ci];
+      }
+    }
+    h->tuned_group[t] = best_g;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!ok || !hip_ok(h, "autotune")) {
+    for (int t = 0; t < 3; ++t) h->tuned_group[t] = -1;
+    if (h->err.empty()) h->err = "autotune: a split GEMM could not be launched";
+    return TATRG_EHIP;
+  }
+  if (h_choice)
+    for (int t = 0; t < 3; ++t) h_choice[t] = h->tuned_group[t];
+  return TATRG_OK;
 }
 
 tatrg_status tatrg_get_record(tatrg_handle* h, int32_t b, int32_t step, int32_t which,

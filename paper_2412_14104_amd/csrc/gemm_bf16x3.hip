@@ -348,7 +348,7 @@ size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given) {
 
 bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
                  hipStream_t st, hipEvent_t ev_after_split, const Bf16PlanesIn* b_in,
-                 const Bf16PlanesOut* c_out) {
+                 const Bf16PlanesOut* c_out, int group_m) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return true;
   // the planes of the split operands must fit the workspace: launch nothing otherwise
   if (!planes_ws || planes_ws_doubles < gemm_bf16x3_ws_doubles(g, b_in != nullptr))
@@ -384,7 +384,7 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
   ba.sBp = b_in ? b_in->stride : (bb_n == 1) ? 0 : g.N * Kp;
   ba.tiles_m = (int)((g.M + BM - 1) / BM);
   ba.tiles_n = (int)((g.N + BN - 1) / BN);
-  ba.group_m = ba.tiles_m >= 12 ? 6 : 0;
+  ba.group_m = group_m >= 0 ? group_m : (ba.tiles_m >= 12 ? 6 : 0);
   ba.cR2 = c_out ? c_out->R2 : 1;
   ba.cC1 = c_out ? c_out->C1 : 1;
   ba.cC2 = c_out ? c_out->C2 : 1;

@@ -146,6 +146,16 @@ int tatrg_test_chol_inv(const double* G, double* R, double* Rinv, int n, int pas
   return launched();
 }
 
+int tatrg_test_chol_inv_batched(const double* G, double* R, double* Rinv, int n, int pass,
+                                double shift_coef, int* fail, int batch, void* stream) {
+  if (!G || !R || !Rinv || !fail || n < 1 || n > 96 || pass < 0 || pass > 2 || batch < 1)
+    return -1;
+  const int64_t s = (int64_t)n * n;
+  chol_inv(G, R, Rinv, n, pass, fail, (hipStream_t)stream, shift_coef, nullptr, batch, s, s, s,
+           1);
+  return launched();
+}
+
 int tatrg_test_philox(double* out, int64_t rows, int64_t cols, uint64_t seed, uint32_t step,
                       uint32_t site, void* stream) {
   if (!out || rows < 1 || cols < 1) return -1;

@@ -463,6 +463,34 @@ def test_chol_inv_flags_a_singular_gram(lib):
     assert not host(dr).any()
 
 
+def test_chol_inv_batched_flags_each_entry(lib):
+    """Three Grams in one launch, the middle one singular: its flag reads pass + 1 and its
+    factors stay unwritten, the other two match the single-matrix kernel bit for bit."""
+    n = 40
+    rng = np.random.default_rng(8)
+    grams = []
+    for b in range(3):
+        y = rng.standard_normal((3 * n, n)) * np.logspace(0, -3, n)[None, :]
+        if b == 1:
+            y[:, 7] = 0.0
+        grams.append(y.T @ y)
+    g = dev(np.stack(grams))
+    dr = torch.zeros((3, n, n), dtype=torch.float64, device="cuda")
+    dri = torch.zeros((3, n, n), dtype=torch.float64, device="cuda")
+    fail = torch.zeros(3, dtype=torch.int32, device="cuda")
+    assert lib.tatrg_test_chol_inv_batched(vp(g), vp(dr), vp(dri), n, 1, 0.0, vp(fail), 3,
+                                           stream()) == 0
+    assert list(host(fail)) == [0, 2, 0]
+    assert not host(dr)[1].any() and not host(dri)[1].any()
+    for b in (0, 2):
+        r1 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        ri1 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        f1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+        assert lib.tatrg_test_chol_inv(vp(dev(grams[b])), vp(r1), vp(ri1), n, 1, 0.0, vp(f1),
+                                       stream()) == 0
+        assert np.array_equal(host(dr)[b], host(r1)) and np.array_equal(host(dri)[b], host(ri1))
+
+
 def test_philox_sketch_matches_oracle(lib):
     from oracle import philox
     for (rows, cols, seed, step, site) in [(7, 5, 0, 0, 0), (1000, 96, 0, 39, 0),

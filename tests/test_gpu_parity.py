@@ -256,3 +256,24 @@ def test_speculative_step_replays_exactly(pkg):
     print("replays", reps.value, flush=True)
     assert reps.value >= 1
     assert f == f_ref and l == l_ref, (f, f_ref)
+
+
+def test_autotuned_split_run_is_bit_identical(pkg):
+    """tatrg_autotune only reorders the split GEMMs' work-groups: a tuned chi = 16 split run
+    gives the untuned run's free energy bit for bit, and the choices are from the table."""
+    g = golden("C2")
+    run = g["runs"][0]
+    ref = pkg.Engine(g["chi"], g["r"], g["q"], 12, seed=g["seed"], precision=pkg.BF16X3,
+                     record_spectra=False)
+    f_ref, l_ref = ref.run(run["beta"])
+    eng = pkg.Engine(g["chi"], g["r"], g["q"], 12, seed=g["seed"], precision=pkg.BF16X3,
+                     record_spectra=False)
+    eng.init(run["beta"])
+    choice = eng.autotune()
+    print("autotune choice", choice, flush=True)
+    assert all(c in (0, 2, 4, 6, 8, 12) for c in choice)
+    for _ in range(12):
+        eng.step()
+    f, l = eng.free_energy()
+    assert f == f_ref and l == l_ref
+    assert pkg.Engine(6, 2, 2, 2).autotune() == [-1, -1, -1]
