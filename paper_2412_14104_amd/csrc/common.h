@@ -65,6 +65,11 @@ bool gemm_bf16x3(const GemmArgs& g, double* planes_ws, size_t planes_ws_doubles,
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given = false);
 // K rounded up to the split GEMM's step of 32 (the row length of its planes).
 int64_t bf16x3_kpad(int64_t K);
+// The three bf16 planes of the contraction operand FM4[(i4a a)][(g k4 kX)] as op(B) of the
+// split GEMM ([N][Kp] with N = (g k4 kX), K = (i4a a) = c^2, zero for K <= k < Kp), read
+// straight from tmp[(i4a k4)][(a kX g)] (extents c, c, c, L, c): the planes split3 would make
+// of FM4, bit for bit.  planes: 3 N Kp elements (cap); false, launching nothing, when short.
+bool fm4_planes(const double* tmp, int c, int L, uint16_t* planes, int64_t cap, hipStream_t st);
 // Products every later split GEMM runs: 6 (the engine) or 3 (i + j <= 1, an accuracy
 // ablation).  Returns the previous count, -1 for another n.  Process-wide.
 int set_split_products(int n);

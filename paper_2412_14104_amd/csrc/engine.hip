@@ -295,6 +295,12 @@ struct Carver {
   }
 };
 
+// The three bf16 planes of FM4, [(g k4 kX)][Kp] each with Kp = chi^2 rounded up to 32, in
+// doubles.
+int64_t fm4_planes_doubles(const Dims& d) {
+  return (3 * d.L * d.n2 * bf16x3_kpad(d.n2) * 2 + 7) / 8;
+}
+
 // The three bf16 planes of P, [i1][(g k4)][Kp] each with Kp = L^2 rounded up to 32, in
 // doubles.
 int64_t p_planes_doubles(const Dims& d) {
@@ -369,7 +375,8 @@ void carve(tatrg_handle* h, Carver& cv) {
   h->Msq = cv.take(3 * n2 * c); h->Nsq = cv.take(3 * n2 * c);
   h->Fp = cv.take(L * n3);
   h->tmp5 = cv.take(L * n4);
-  h->FM4 = cv.take(L * n4);
+  // FM4 in float64 on the FP64 path, its three bf16 planes on the split path
+  h->FM4 = cv.take(std::max(L * n4, fm4_planes_doubles(d)));
   // P in float64; on the split path the P GEMM writes P's bf16 planes here instead
   h->P = cv.take(std::max(L * L * n3, p_planes_doubles(d)));
   h->q1 = cv.take(std::max(L * n3, L * L * n2));  // [(i3a kA),(i2b k2)] then [(kA k2 k3), kX]
@@ -1121,12 +1128,19 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
   uint16_t* pp = reinterpret_cast<uint16_t*>(h->P);
   const int64_t pn = c * n2 * Kp;  // elements per plane of P
   if (split) {
-    // FM4[i4a][a][g][k4][kX], kX innermost: the P GEMM's columns are (g k4, kX) and its
-    // epilogue writes P's planes [i1][(g k4)][(kA kX)], K-contiguous for Qt^T.P
-    perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 4, 1, 3});
+    // FM4[i4a][a][g][k4][kX], kX innermost, goes straight from tmp5 into the bf16 planes the
+    // P GEMM reads (it is never stored in float64); the P GEMM's columns are (g k4, kX) and
+    // its epilogue writes P's planes [i1][(g k4)][(kA kX)], K-contiguous for Qt^T.P
+    uint16_t* fp = reinterpret_cast<uint16_t*>(h->FM4);
+    const int64_t fn = L * n2 * bf16x3_kpad(n2);
+    if (!fm4_planes(h->tmp5, (int)c, (int)L, fp, 4 * fm4_planes_doubles(d), h->st)) {
+      h->err = "FM4 plane workspace too small";
+      h->host_fault = true;
+    }
+    const Bf16PlanesIn fi = {{fp, fp + fn, fp + 2 * fn}, 0};
     const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, L, n2, L, Kp, 0, pn};
-    gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, nullptr, 0),
-               nullptr, &po, h->tuned_group[0]);
+    gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, nullptr, L * n2, false, nullptr, 0), &fi,
+               &po, h->tuned_group[0]);
   } else {
     // FM4[i4a][a][kX][g][k4]
     perm(h, h->tmp5, h->FM4, {c, c, c, L, c}, {0, 2, 3, 4, 1});
@@ -1735,7 +1749,10 @@ tatrg_status tatrg_autotune(tatrg_handle* h, int32_t* h_choice) {
   uint16_t* pp = reinterpret_cast<uint16_t*>(h->P);
   const Bf16PlanesOut po = {{pp, pp + pn, pp + 2 * pn}, L, n2, L, Kp, 0, pn};
   const Bf16PlanesIn pi = {{pp, pp + pn, pp + 2 * pn}, n2 * Kp};
-  const GemmArgs gP = G(c * L, L * n2, n2, h->E, n2, false, h->FM4, L * n2, false, nullptr, 0);
+  uint16_t* fp = reinterpret_cast<uint16_t*>(h->FM4);
+  const int64_t fn = L * n2 * bf16x3_kpad(n2);
+  const Bf16PlanesIn fi = {{fp, fp + fn, fp + 2 * fn}, 0};
+  const GemmArgs gP = G(c * L, L * n2, n2, h->E, n2, false, nullptr, L * n2, false, nullptr, 0);
   const GemmArgs gPhi =
       Gb(G(n2, n2, L * L, h->Qt, n2, true, nullptr, 0, false, h->phin, n2), c, 0, 0, d.n4);
   const GemmArgs gS = G(n2, c * w, n3, h->cp, n2, true, h->P2, c * w, false, h->t1, c * w);
@@ -1752,7 +1769,7 @@ tatrg_status tatrg_autotune(tatrg_handle* h, int32_t* h_choice) {
     for (int ci = 0; ci < 6 && ok; ++ci) {
       auto run = [&]() {
         if (t == 0)
-          ok = ok && gemm_bf16x3(gP, h->planes, h->planes_doubles, h->st, nullptr, nullptr, &po,
+          ok = ok && gemm_bf16x3(gP, h->planes, h->planes_doubles, h->st, nullptr, &fi, &po,
                                  cand[ci]);
         else if (t == 1)
           ok = ok && gemm_bf16x3(gPhi, h->planes, h->planes_doubles, h->st, nullptr, &pi,

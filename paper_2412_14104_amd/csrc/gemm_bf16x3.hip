@@ -327,6 +327,49 @@ int64_t plane_batches(const GemmArgs& g, bool a_side) {
   return s == 0 ? 1 : g.batch;
 }
 
+// The planes of the contraction's FM4 operand straight from tmp[(i4a k4)][(a kX g)] (leg
+// extents c, c, c, L, c): plane row n = (g, k4, kX), column k = (i4a, a), i.e. FM4 with kX
+// innermost, transposed to the k-contiguous layout the split GEMM reads, without storing FM4
+// in float64.  One 32 x 32 tile of (a, g) per work-group for one (i4a, k4, kX), transposed
+// through LDS; every value is split exactly as split3_kernel splits it.
+__global__ __launch_bounds__(256) void fm4_planes_kernel(const double* __restrict__ tmp, int c,
+                                                         int L, int64_t Kp,
+                                                         uint16_t* __restrict__ p0,
+                                                         uint16_t* __restrict__ p1,
+                                                         uint16_t* __restrict__ p2) {
+  __shared__ double tile[32][33];  // [a][g]
+  const int tid = threadIdx.x;
+  const int64_t blk = blockIdx.x;   // (i4a, k4, kX)
+  const int kX = (int)(blk % L);
+  const int k4 = (int)((blk / L) % c);
+  const int i4a = (int)(blk / ((int64_t)L * c));
+  const int a0 = 32 * (int)blockIdx.y, g0 = 32 * (int)blockIdx.z;
+  // tmp row (i4a k4), column (a kX g): contiguous in g
+  const double* src = tmp + ((int64_t)i4a * c + k4) * ((int64_t)c * L * c);
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int aa = idx / 32, gg = idx % 32;
+    const int a = a0 + aa, g = g0 + gg;
+    tile[aa][gg] = (a < c && g < c) ? src[((int64_t)a * L + kX) * c + g] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int gg = idx / 32, aa = idx % 32;
+    const int a = a0 + aa, g = g0 + gg;
+    if (a < c && g < c) {
+      const double v = tile[aa][gg];
+      const uint16_t h0 = bf16_rne((float)v);
+      const double r1 = v - bf16_to_double(h0);
+      const uint16_t h1 = bf16_rne((float)r1);
+      const double r2 = r1 - bf16_to_double(h1);
+      const int64_t row = ((int64_t)g * c + k4) * L + kX;
+      const int64_t o = row * Kp + (int64_t)i4a * c + a;
+      p0[o] = h0;
+      p1[o] = h1;
+      p2[o] = bf16_rne((float)r2);
+    }
+  }
+}
+
 }  // namespace
 
 // Products per split GEMM (6; 3 for the accuracy ablation), process-wide.
@@ -338,6 +381,24 @@ int set_split_products(int n) {
 }
 
 int64_t bf16x3_kpad(int64_t K) { return ((K + BK - 1) / BK) * BK; }
+
+bool fm4_planes(const double* tmp, int c, int L, uint16_t* planes, int64_t cap,
+                hipStream_t st) {
+  const int64_t n2 = (int64_t)c * c, Kp = bf16x3_kpad(n2), rows = (int64_t)L * n2;
+  if (!tmp || !planes || c < 1 || L < 1 || 3 * rows * Kp > cap) return false;
+  uint16_t* p0 = planes;
+  uint16_t* p1 = planes + rows * Kp;
+  uint16_t* p2 = planes + 2 * rows * Kp;
+  if (Kp > n2) {
+    const int64_t n = rows * (Kp - n2);
+    dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 4096), 1u);
+    hipLaunchKernelGGL(zero_plane_tail_kernel, grid, dim3(256), 0, st, p0, p1, p2, rows, n2, Kp,
+                       (int64_t)0);
+  }
+  dim3 grid((unsigned)((int64_t)c * c * L), (unsigned)((c + 31) / 32), (unsigned)((c + 31) / 32));
+  hipLaunchKernelGGL(fm4_planes_kernel, grid, dim3(256), 0, st, tmp, c, L, Kp, p0, p1, p2);
+  return true;
+}
 
 size_t gemm_bf16x3_ws_doubles(const GemmArgs& g, bool b_given) {
   const int64_t Kp = bf16x3_kpad(g.K);

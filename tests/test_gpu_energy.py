@@ -95,3 +95,13 @@ def test_triples_are_validated(pkg):
         eng.step()
     l0, d1, d2 = eng.lnz_derivatives()
     assert len(l0) == 1 and d1[0] > 0
+
+
+def test_triples_of_a_batch_equal_single_triples(pkg):
+    """Several temperatures in one batch (two triples) give each triple's derivatives bit for
+    bit, as the batch entries run the same kernels with the same sketches in turn."""
+    from paper_2412_14104_amd.energy import derivatives
+    both = derivatives([0.14, 0.16], 6, 2, 2, 8)
+    for i, beta in enumerate((0.14, 0.16)):
+        one = derivatives([beta], 6, 2, 2, 8)
+        assert [v[i] for v in both] == [v[0] for v in one]
