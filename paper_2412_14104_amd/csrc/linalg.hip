@@ -349,9 +349,18 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* Ain, dou
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const double* A = Ain + (int64_t)blockIdx.x * n * n;
 
-  for (int idx = tid; idx < ne * n; idx += blockDim.x) {
-    const int p = idx / n, i = idx - (idx / n) * n;
-    W[idx] = (p < n) ? A[i * n + p] : 0.0;
+  {
+    // ne n <= 96 x 96 = 9 x 1024 entries (launched with 1024 threads): all loads in flight
+    // before the LDS writes
+    double v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int idx = tid + t * 1024, p = idx / n, i = idx - (idx / n) * n;
+      v[t] = (idx < ne * n && p < n) ? A[i * n + p] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (tid + t * 1024 < ne * n) W[tid + t * 1024] = v[t];
   }
   for (int idx = tid; idx < ne * ne; idx += blockDim.x) {
     const int p = idx / ne, i = idx - (idx / ne) * ne;
@@ -872,8 +881,16 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(double* Aall, double*
   double* A = Aall + (int64_t)blockIdx.y * n * n;
   double* Di = Dinv + ((int64_t)blockIdx.y * ((n + 63) / 64) + j / 64) * 64 * 64;
   const int r = threadIdx.x;
-  for (int rr = 0; rr < jb; ++rr)
-    blk[rr][r] = (r < jb) ? A[(int64_t)(j + rr) * n + j + r] : 0.0;
+  {
+    // all 64 loads in flight before the first LDS write (a load-then-store loop would wait
+    // for each row in turn)
+    double v[64];
+#pragma unroll
+    for (int rr = 0; rr < 64; ++rr)
+      v[rr] = (rr < jb && r < jb) ? A[(int64_t)(j + rr) * n + j + r] : 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 64; ++rr) blk[rr][r] = v[rr];
+  }
   __syncthreads();
   double row[64];
 #pragma unroll
