@@ -126,9 +126,12 @@ void cholesky_shifted_inv(double* A, double* Dinv, int n, int batch, double shif
 // Inverse of `batch` lower-triangular n x n matrices L (stride n*n) whose 64 x 64 diagonal
 // blocks are already inverted in Dinv (as cholesky_blocked_inv leaves them), by doubling the
 // inverted blocks: the off-diagonal block of [[A, 0], [B, C]]^{-1} is -C^{-1} B A^{-1}.
-// Linv: batch x n x n; T: scratch of at least n * n / 2 doubles.
+// Linv: batch x n x n; T: scratch of at least n * n / 2 doubles.  With `partial` (device,
+// partial_doubles), the products of the upper levels, which have few output tiles, are split
+// along K through it.
 void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T, int n,
-                   int batch, hipStream_t st);
+                   int batch, hipStream_t st, double* partial = nullptr,
+                   size_t partial_doubles = 0);
 
 // Checks the diagonal of `batch` lower Cholesky factors (n x n, stride n*n): ORs `code` into
 // *flag when a diagonal entry is not finite or not positive, when the smallest pivot L_ii^2

@@ -796,16 +796,18 @@ void compress_swap_panels(tatrg_handle* h) {
   chol_check(h->cg, (int)n2, 2, 0.0, 0.0, INFINITY, h->cflag, st, 8);
   cholesky_blocked_inv(h->cg, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st, 2);
-  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st, h->partial,
+                h->partial_doubles);
   // Q1 = P L1^{-T}
   gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st, 4);
-  tri_inv_lower(h->cg2, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st);
+  tri_inv_lower(h->cg2, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st, h->partial,
+                h->partial_doubles);
   h->cqx = h->cq;
   // ctt = L1 L2 = R^^T, rows (x g); ct[(x b)] = sum_g S'[b, g] ctt[(x g)] (S' is symmetric)
-  gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ctt, n2), 2, s2, s2, s2));
+  gemm_long_k(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ctt, n2), 2, s2, s2, s2));
   weights_into_r(h);
 }
 
@@ -832,22 +834,25 @@ void compress_swap_panels_shifted(tatrg_handle* h) {
   zero((double*)h->cflag, 1, st);
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
   cholesky_shifted_inv(h->cg, h->cdi, (int)n2, 2, shift, h->cflag, st);
-  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  tri_inv_lower(h->cg, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st, h->partial,
+                h->partial_doubles);
   gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg2, (int)n2, 2, 1e-15, 0.0, INFINITY, h->cflag, st, 2);
-  tri_inv_lower(h->cg2, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st);
+  tri_inv_lower(h->cg2, h->cdi, h->cli1, h->ctmp, (int)n2, 2, st, h->partial,
+                h->partial_doubles);
   // Q2 = Q1 L2^{-T} into cp (the panels are no longer needed)
   gemm(h, Gb(G(n3, n2, n2, h->cq, n2, false, h->cli1, n2, true, h->cp, n2), 2, n5, s2, n5));
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg3, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg3, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg3, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st, 4);
-  tri_inv_lower(h->cg3, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st);
+  tri_inv_lower(h->cg3, h->cdi, h->cli2, h->ctmp, (int)n2, 2, st, h->partial,
+                h->partial_doubles);
   h->cqx = h->cp;
   // ctt = L1 L2 L3
-  gemm(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ct, n2), 2, s2, s2, s2));
-  gemm(h, Gb(G(n2, n2, n2, h->ct, n2, false, h->cg3, n2, false, h->ctt, n2), 2, s2, s2, s2));
+  gemm_long_k(h, Gb(G(n2, n2, n2, h->cg, n2, false, h->cg2, n2, false, h->ct, n2), 2, s2, s2, s2));
+  gemm_long_k(h, Gb(G(n2, n2, n2, h->ct, n2, false, h->cg3, n2, false, h->ctt, n2), 2, s2, s2, s2));
   weights_into_r(h);
 }
 
@@ -908,11 +913,11 @@ bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
     rsvd(h, op, d.n3, d.n3, w, h->cfg.q, SITE_SWAP, h->P2, h->P1, false, true, true);
     // U~ = Q Uh[:, :c] as [p][(alpha g)]; X rows (f', alpha) = Q_A U~ = Q1A (L2A^{-T} U~)
     gemm(h, G(d.n3, c, w, h->P2, w, false, h->Uh, w, false, h->t1, c));
-    gemm(h, G(d.n2, d.n2, d.n2, L2iA, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
+    gemm_long_k(h, G(d.n2, d.n2, d.n2, L2iA, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
     gemm(h, G(d.n3, d.n2, d.n2, Q1A, d.n2, false, h->t2, d.n2, false, h->Xs, d.n2));
     perm(h, h->Xs, h->X, {d.n3, c, c}, {1, 0, 2});
     gemm(h, G(d.n3, c, w, h->P1, w, false, h->Vh, w, false, h->t1, c));
-    gemm(h, G(d.n2, d.n2, d.n2, L2iB, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
+    gemm_long_k(h, G(d.n2, d.n2, d.n2, L2iB, d.n2, true, h->t1, d.n2, false, h->t2, d.n2));
     gemm(h, G(d.n3, d.n2, d.n2, Q1B, d.n2, false, h->t2, d.n2, false, h->Xs, d.n2));
     perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
   } else {
@@ -992,6 +997,14 @@ void isometries(tatrg_handle* h) {
 void triad(tatrg_handle* h) {
   const Dims& d = h->d;
   const int64_t c = d.c, n2 = d.n2, L = d.L;
+  // c products of L x n2 x n2: one row of output tiles each, so in two halves of K (two
+  // resident work-groups per CU instead of one) when the partial sums fit
+  auto gemm = [&](tatrg_handle* hh, const GemmArgs& g) {
+    if ((size_t)(2 * g.batch * g.M * g.N) <= hh->partial_doubles)
+      gemm_f64_splitk(g, 2, hh->partial, hh->st);
+    else
+      gemm_f64(g, hh->st);
+  };
   const double* UA = h->UZ;
   const double* UX = h->UZ + n2 * L;
   const double* UY = h->UZ + 2 * n2 * L;
@@ -1052,7 +1065,7 @@ void squeezers(tatrg_handle* h, double* rec) {
     gemm_long_k(h, G(n2, n2, n3, h->pm3, n3, false, h->pm3, n3, true, h->sq2, n2));
     perm(h, h->sq1, h->sq3, d4, {0, 2, 1, 3});
     perm(h, h->sq2, h->sq4, d4, {0, 2, 1, 3});
-    gemm(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
+    gemm_long_k(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
     perm(h, h->sq1, rl, d4, {0, 2, 1, 3});
     // rho_R = sum_{b b'} yy[b v1 b' v1'] dd[v2 b v2' b']
     perm(h, h->yg, h->pm3, d5, x_perm[mi]);
@@ -1061,7 +1074,7 @@ void squeezers(tatrg_handle* h, double* rec) {
     gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
     perm(h, h->sq2, h->sq3, d4, {1, 3, 0, 2});
     perm(h, h->sq1, h->sq4, d4, {1, 3, 0, 2});
-    gemm(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
+    gemm_long_k(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
     perm(h, h->sq1, rr, d4, {0, 2, 1, 3});
   }
   symmetrize(h->rho, (int)n2, 6, st);
@@ -1073,8 +1086,8 @@ void squeezers(tatrg_handle* h, double* rec) {
   // (rho_L + shift = Ll Ll^T, R_L = Ll^T; R_R = Lr^T), into the Grams' space, then one batched
   // randomized SVD of the three (Q in P2, Qb in P1, cores in Uhb, Shb, Vhb)
   const int w = d.L;
-  gemm(h, Gb(G(n2, n2, n2, h->chol, n2, true, h->chol + 3 * n2 * n2, n2, false, h->rho, n2), 3,
-             n2 * n2, n2 * n2, n2 * n2));
+  gemm_long_k(h, Gb(G(n2, n2, n2, h->chol, n2, true, h->chol + 3 * n2 * n2, n2, false, h->rho, n2),
+                    3, n2 * n2, n2 * n2, n2 * n2));
   rsvd_b(h, h->rho, n2 * n2, 3, n2, w, sq_sites, h->P2, h->P1, false);
   for (int mi = 0; mi < 3; ++mi) {
     const double* Ll = h->chol + mi * n2 * n2;
@@ -1099,11 +1112,11 @@ void squeezers(tatrg_handle* h, double* rec) {
     // M = (R_R^T V D) O = (Lr V D) O  (n2 x c), stored [u1][u2][k]; rotating after the
     // S^-1/2 weights keeps M N = R_R^T V S^-1 U^T R_L for any O.
     double* M = h->Msq + mi * n2 * c;
-    gemm(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
+    gemm_long_k(h, G(n2, c, n2, Lr, n2, false, h->Vsq, c, false, h->Vmat, c));
     scale_cols(h->Vmat, h->Dm, n2, c, c, st);
     gemm(h, G(n2, c, c, h->Vmat, c, false, h->Oc, c, false, M, c));
     // N = O^T (D U^T R_L) = ((Ll U D) O)^T  (c x n2), stored [k][v1][v2]
-    gemm(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
+    gemm_long_k(h, G(n2, c, n2, Ll, n2, false, h->Usq, c, false, h->Umat, c));
     scale_cols(h->Umat, h->Dm, n2, c, c, st);
     gemm(h, G(n2, c, c, h->Umat, c, false, h->Oc, c, false, h->Vsq, c));
     transpose_batched(h->Vsq, h->Nsq + mi * n2 * c, (int)n2, (int)c, 1, st);

@@ -166,7 +166,22 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
     beta = g.beta;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
+    // the old C of a row block is loaded before any of its stores, so the loads are in flight
+    // together (interleaved, each store would wait for its own load); out-of-range entries read
+    // the nearest in-range one (unused), so the loads need no per-entry branch
+    double cold[TN][4];
+    if (!PLAIN && beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
+          const int64_t col = n0 + wn * TN * 16 + j * 16 + (lane & 15);
+          const int64_t rc = row < M ? row : M - 1, cc = col < N ? col : N - 1;
+          cold[j][v] = C[rc * ldc + cc];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -178,11 +193,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(KArgs ka) {
             C[row * ldc + col] = acc[i][j][v];
           } else {
             double val = alpha * acc[i][j][v];
-            if (beta != 0.0) val += beta * C[row * ldc + col];
+            if (beta != 0.0) val += beta * cold[j][v];
             C[row * ldc + col] = val;
           }
         }
       }
+  }
 }
 
 // C[b] = alpha * sum_p partial[b][p] + beta * C[b], parts summed in increasing p.  With sym,

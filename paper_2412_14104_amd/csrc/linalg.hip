@@ -1014,8 +1014,21 @@ void cholesky_shifted_inv(double* A, double* Dinv, int n, int batch, double shif
 }
 
 void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T, int n,
-                   int batch, hipStream_t st) {
+                   int batch, hipStream_t st, double* partial, size_t partial_doubles) {
   const int64_t s2 = (int64_t)n * n;
+  // a product with fewer than 64 output tiles runs split along K (parts of >= 64) when the
+  // partial-sum buffer holds them: one work-group per tile would leave most of the chip idle
+  auto run = [&](const GemmArgs& g) {
+    const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+    const int64_t mn = g.M * g.N * g.batch;
+    int64_t parts = std::min<int64_t>(g.K / 64, 8);
+    if (partial && mn > 0)
+      parts = std::min<int64_t>(parts, (int64_t)(partial_doubles / (size_t)mn));
+    if (partial && tiles < 64 && parts >= 2)
+      gemm_f64_splitk(g, (int)parts, partial, st);
+    else
+      gemm_f64(g, st);
+  };
   {
     const int64_t total = s2 * batch;
     int64_t blocks = (total + 255) / 256;
@@ -1033,19 +1046,19 @@ void tri_inv_lower(const double* L, const double* Dinv, double* Linv, double* T,
       double* Xb = Linv + b * s2;
       if (pairs_full > 0) {
         // T_i = B_i A_i^{-1}, X21_i = -C_i^{-1} T_i, for the pairs at o = 2 s i
-        gemm_f64(gemm_args(s, s, s, Lb + (int64_t)s * n, n, false, Xb, n, false, T, s, 1.0, 0.0,
-                           pairs_full, stride, stride, (int64_t)s * s), st);
-        gemm_f64(gemm_args(s, s, s, Xb + (int64_t)s * n + s, n, false, T, s, false,
+        run(gemm_args(s, s, s, Lb + (int64_t)s * n, n, false, Xb, n, false, T, s, 1.0, 0.0,
+                           pairs_full, stride, stride, (int64_t)s * s));
+        run(gemm_args(s, s, s, Xb + (int64_t)s * n + s, n, false, T, s, false,
                            Xb + (int64_t)s * n, n, -1.0, 0.0, pairs_full, stride,
-                           (int64_t)s * s, stride), st);
+                           (int64_t)s * s, stride));
       }
       const int o = pairs_full * 2 * s;
       const int sc = n - o - s;  // a last, partial pair: A of size s, C of size sc < s
       if (sc > 0) {
-        gemm_f64(gemm_args(sc, s, s, Lb + (int64_t)(o + s) * n + o, n, false,
-                           Xb + (int64_t)o * n + o, n, false, T, s, 1.0, 0.0, 1, 0, 0, 0), st);
-        gemm_f64(gemm_args(sc, s, sc, Xb + (int64_t)(o + s) * n + o + s, n, false, T, s, false,
-                           Xb + (int64_t)(o + s) * n + o, n, -1.0, 0.0, 1, 0, 0, 0), st);
+        run(gemm_args(sc, s, s, Lb + (int64_t)(o + s) * n + o, n, false,
+                           Xb + (int64_t)o * n + o, n, false, T, s, 1.0, 0.0, 1, 0, 0, 0));
+        run(gemm_args(sc, s, sc, Xb + (int64_t)(o + s) * n + o + s, n, false, T, s, false,
+                           Xb + (int64_t)(o + s) * n + o, n, -1.0, 0.0, 1, 0, 0, 0));
       }
     }
   }
