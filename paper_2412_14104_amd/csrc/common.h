@@ -178,6 +178,9 @@ void philox_words(uint32_t* out, int64_t pair0, int64_t npairs, uint64_t seed, u
 void permute(const double* in, double* out, int rank, const int64_t* dims, const int* perm,
              hipStream_t st);
 
+// y = x diag(s) for a rows x cols row-major x (y, x distinct).
+void copy_scale_cols(double* y, const double* x, const double* s, int64_t rows, int64_t cols,
+                     hipStream_t st);
 // x[i][j] *= s[j] for an rows x cols row-major matrix (ld).
 void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t ld,
                 hipStream_t st);

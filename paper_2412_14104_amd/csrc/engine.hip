@@ -962,10 +962,8 @@ void isometries(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int64_t c = d.c, n2 = d.n2;
-  copy(h->Xs, h->X, d.n5, st);
-  scale_cols(h->Xs, h->sig, d.n4, c, c, st);
-  copy(h->Ys, h->Y, d.n5, st);
-  scale_cols(h->Ys, h->sig, d.n4, c, c, st);
+  copy_scale_cols(h->Xs, h->X, h->sig, d.n4, c, st);
+  copy_scale_cols(h->Ys, h->Y, h->sig, d.n4, c, st);
   // P_X = (X sigma)(X sigma)^T and P_Y alike (c x c, semidefinite), side by side in the
   // batched scratch, and factors L L^T = P: rho_A = sum A P_X A^T = (A L_X)(A L_X)^T is then a
   // symmetric Gram (half the tiles of the product), and rho_D alike
@@ -1061,15 +1059,24 @@ void squeezers(tatrg_handle* h, double* rec) {
     // rho_L = sum_{a a'} aa[u1 a u1' a'] xx[a u2 a' u2']
     perm(h, h->Ah, h->pm1, d5, a_perm[mi]);
     gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
-    perm(h, h->xg, h->pm3, d5, x_perm[mi]);
-    gemm_long_k(h, G(n2, n2, n3, h->pm3, n3, false, h->pm3, n3, true, h->sq2, n2));
+    // (x_perm[0] is the identity: xg is used as it is)
+    const double* xs = h->xg;
+    if (mi > 0) {
+      perm(h, h->xg, h->pm3, d5, x_perm[mi]);
+      xs = h->pm3;
+    }
+    gemm_long_k(h, G(n2, n2, n3, xs, n3, false, xs, n3, true, h->sq2, n2));
     perm(h, h->sq1, h->sq3, d4, {0, 2, 1, 3});
     perm(h, h->sq2, h->sq4, d4, {0, 2, 1, 3});
     gemm_long_k(h, G(n2, n2, n2, h->sq3, n2, false, h->sq4, n2, false, h->sq1, n2));
     perm(h, h->sq1, rl, d4, {0, 2, 1, 3});
     // rho_R = sum_{b b'} yy[b v1 b' v1'] dd[v2 b v2' b']
-    perm(h, h->yg, h->pm3, d5, x_perm[mi]);
-    gemm_long_k(h, G(n2, n2, n3, h->pm3, n3, false, h->pm3, n3, true, h->sq2, n2));
+    const double* ys = h->yg;
+    if (mi > 0) {
+      perm(h, h->yg, h->pm3, d5, x_perm[mi]);
+      ys = h->pm3;
+    }
+    gemm_long_k(h, G(n2, n2, n3, ys, n3, false, ys, n3, true, h->sq2, n2));
     perm(h, h->Dh, h->pm1, d5, a_perm[mi]);
     gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
     perm(h, h->sq2, h->sq3, d4, {1, 3, 0, 2});

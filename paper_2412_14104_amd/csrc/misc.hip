@@ -186,6 +186,16 @@ __global__ void scale_cols_kernel(double* x, const double* s, int64_t rows, int6
   }
 }
 
+// y = x diag(s) for a rows x cols row-major x (one pass instead of a copy and a scaling).
+__global__ void copy_scale_cols_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                       const double* __restrict__ s, int64_t rows,
+                                       int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    y[idx] = x[idx] * s[idx % cols];
+}
+
 // U[b] <- U[b] diag(sqrt(S[b])) for `batch` n x n matrices (strides n^2 and n).
 __global__ void sqrt_scale_cols_kernel(double* U, const double* S, int n, int batch) {
   const int64_t total = (int64_t)batch * n * n;
@@ -391,6 +401,12 @@ void permute(const double* in, double* out, int rank, const int64_t* dims, const
     return;
   }
   hipLaunchKernelGGL(permute_kernel, dim3(grid_for(s)), dim3(TPB), 0, st, in, out, pa, s);
+}
+
+void copy_scale_cols(double* y, const double* x, const double* s, int64_t rows, int64_t cols,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(copy_scale_cols_kernel, dim3(grid_for(rows * cols)), dim3(TPB), 0, st, y, x,
+                     s, rows, cols);
 }
 
 void scale_cols(double* x, const double* s, int64_t rows, int64_t cols, int64_t ld,
