@@ -161,6 +161,14 @@ struct tatrg_handle {
   tatrg_config cfg;
   Dims d;
   hipStream_t st;
+  // Side stream of the compressed bond swap: the swap's sketch and its map through the first
+  // orthonormal factor are independent of the panels' Cholesky chains (latency bound, two
+  // work-groups), so they run beside them (fork events on st, a join event on st2).
+  hipStream_t st2 = nullptr;  // created at the first step (st itself if that fails)
+  bool st2_tried = false;
+  hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
+  bool side_ok = false;  // t1 holds the sketch map of the current step (Q1B of the first pass)
+  double* partial2 = nullptr;  // split-K partial sums of the side stream (FP64 path)
   std::string err;
   int step = 0;
   bool initialized = false;
@@ -400,6 +408,7 @@ void carve(tatrg_handle* h, Carver& cv) {
   }
   h->partial_doubles = splitk_partial_doubles(d);
   h->partial = cv.take(h->partial_doubles);
+  h->partial2 = cv.take(h->partial_doubles);
   h->probe = cv.take((size_t)N_PROBES * n4);
   h->trace_part = cv.take(4096);
   // core factors of an RSVD of any width up to MAX_W (the step's widths are L and Ls; the
@@ -462,15 +471,16 @@ void gemm_timed(tatrg_handle* h, const GemmArgs& g, const Bf16PlanesIn* b_in = n
 // Deterministic split-K for products with a small output and a long K.  The part count fills
 // whole rounds of the chip (256 CUs x 2 resident GEMM work-groups) with the tiles that run
 // -- for a symmetric product only those on and above the diagonal -- keeping at least 128
-// values of K per part and within the partial-sum buffer.
-void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
-  if (g.K >= 4096 && gram_tn(g, h->partial, h->partial_doubles, h->st)) return;
+// values of K per part and within the partial-sum buffer `partial` of the stream st (partial on
+// the handle's stream, partial2 on its side stream).
+void gemm_long_k_on(tatrg_handle* h, const GemmArgs& g, double* partial, hipStream_t st) {
+  if (g.K >= 4096 && gram_tn(g, partial, h->partial_doubles, st)) return;
   constexpr int64_t SLOTS = 512;
   const int64_t mn = g.M * g.N * g.batch;
   const int64_t tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
   const int64_t tiles = tm * tn * g.batch;
   if (tiles >= 256) {
-    gemm_f64(g, h->st);
+    gemm_f64(g, st);
     return;
   }
   GemmArgs gs = g;
@@ -483,11 +493,13 @@ void gemm_long_k(tatrg_handle* h, const GemmArgs& g) {
   while (parts > cap && rounds > 1) parts = --rounds * SLOTS / active;
   parts = std::min(parts, cap);
   if (parts < 2) {
-    gemm_f64(g, h->st);
+    gemm_f64(g, st);
     return;
   }
-  gemm_f64_splitk(gs, (int)parts, h->partial, h->st);
+  gemm_f64_splitk(gs, (int)parts, partial, st);
 }
+
+void gemm_long_k(tatrg_handle* h, const GemmArgs& g) { gemm_long_k_on(h, g, h->partial, h->st); }
 
 // dst <- src (m x n panels) when lo <= *flag <= hi.
 __global__ void copy_panel_when_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
@@ -786,12 +798,72 @@ void canonicalize(tatrg_handle* h, int k, double* rec) {
 // pass leaves (0.5, 2).
 void weights_into_r(tatrg_handle* h);
 
+// The side stream, created at first use (default priority) with its fork and join events; the
+// handle's own stream when that fails (the side work then runs in order).
+hipStream_t side_stream(tatrg_handle* h) {
+  if (!h->st2_tried) {
+    h->st2_tried = true;
+    if (hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (h->st2) hipStreamDestroy(h->st2);
+      h->st2 = nullptr;
+    }
+  }
+  return h->st2 ? h->st2 : h->st;
+}
+
+// Orders the side stream after the work enqueued on st so far (fork event i).
+void side_fork(tatrg_handle* h, int i) {
+  if (!h->st2) return;
+  hipEventRecord(h->fork_ev[i], h->st);
+  hipStreamWaitEvent(h->st2, h->fork_ev[i], 0);
+}
+
+// Orders st after the side stream's work (no-op without a side stream or before any join).
+void side_join_wait(tatrg_handle* h) {
+  if (h->st2 && h->join_ev) hipStreamWaitEvent(h->st, h->join_ev, 0);
+}
+
+// The swap's Gaussian sketch (rows (beta, b') stored in (b', beta) order) into P2, on stream st.
+void swap_sketch(tatrg_handle* h, hipStream_t st) {
+  const Dims& d = h->d;
+  philox_gaussian(h->P2, d.n4, d.Ls, d.Ls, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
+                  d.n3);
+}
+
+// The sketch mapped through the first-pass orthonormal factor of the B panel,
+// t1 = Q1B^T Omega (rows (p', beta)), on stream st with the split-K buffer `partial`.  On the
+// split path it runs on the split-bf16 engine: it only maps a Gaussian sketch, whose rounding
+// at 2^-24 moves the randomized SVD's result far below the split path's error.
+void swap_sketch_map(tatrg_handle* h, const double* Q1B, hipStream_t st, double* partial) {
+  const Dims& d = h->d;
+  const int64_t c = d.c, w = d.Ls;
+  const GemmArgs gs = G(d.n2, c * w, d.n3, Q1B, d.n2, true, h->P2, c * w, false, h->t1, c * w);
+  if (h->cfg.precision == TATRG_BF16X3) {
+    if (!gemm_bf16x3(gs, h->planes, h->planes_doubles, st, nullptr, nullptr, nullptr,
+                     h->tuned_group[2])) {
+      h->err = "split-bf16 plane workspace too small for the swap sketch map";
+      h->host_fault = true;
+    }
+  } else {
+    gemm_long_k_on(h, gs, partial, st);
+  }
+}
+
 void compress_swap_panels(tatrg_handle* h) {
   const Dims& d = h->d;
   hipStream_t st = h->st;
   const int64_t c = d.c, n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
   zero((double*)h->cflag, 1, st);
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
+  // side stream: the sketch is drawn while the Cholesky chain below runs (every earlier use of
+  // P2 is ordered before the fork)
+  const hipStream_t side = side_stream(h);
+  side_fork(h, 0);
+  swap_sketch(h, side);
   // a zero column of a panel (a zero diagonal entry of its Gram) is structural rank deficiency
   chol_check(h->cg, (int)n2, 2, 0.0, 0.0, INFINITY, h->cflag, st, 8);
   cholesky_blocked_inv(h->cg, h->cdi, (int)n2, 2, h->cflag, st);
@@ -800,6 +872,12 @@ void compress_swap_panels(tatrg_handle* h) {
                 h->partial_doubles);
   // Q1 = P L1^{-T}
   gemm(h, Gb(G(n3, n2, n2, h->cp, n2, false, h->cli1, n2, true, h->cq, n2), 2, n5, s2, n5));
+  // side stream: the sketch map through Q1B runs while the second pass factors its Gram (the
+  // bond swap uses it when the verdict is a compressed middle from these panels)
+  side_fork(h, 1);
+  swap_sketch_map(h, h->cq + n5, side, h->partial2);
+  if (h->st2) hipEventRecord(h->join_ev, h->st2);
+  h->side_ok = true;
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
   chol_check(h->cg2, (int)n2, 2, 0.0, 0.5, 2.0, h->cflag, st, 4);
@@ -831,6 +909,7 @@ void compress_swap_panels_shifted(tatrg_handle* h) {
   hipStream_t st = h->st;
   const int64_t n2 = d.n2, n3 = d.n3, n5 = d.n5, s2 = n2 * n2;
   const double shift = 11.0 * ((double)n3 * n2 + (double)n2 * (n2 + 1)) * 1.1102230246251565e-16;
+  h->side_ok = false;  // the sketch map of the side stream used the first attempt's factor
   zero((double*)h->cflag, 1, st);
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cp, n2, true, h->cp, n2, false, h->cg, n2), 2, n5, n5, s2));
   cholesky_shifted_inv(h->cg, h->cdi, (int)n2, 2, shift, h->cflag, st);
@@ -889,22 +968,14 @@ bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
     const double* L2iA = h->cli2;
     const double* L2iB = h->cli2 + d.n2 * d.n2;
     // the sketch of M, rows (beta, b') stored in (b', beta) order, then
-    // (Q_B x 1)^T Omega = L2B^{-1} Q1B^T Omega: rows (p', beta)
-    philox_gaussian(h->P2, d.n4, w, w, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
-                    d.n3);
-    const GemmArgs gs = G(d.n2, c * w, d.n3, Q1B, d.n2, true, h->P2, c * w, false, h->t1, c * w);
-    // on the split path the sketch map (2 chi^6 Ls flops, the largest product of the compressed
-    // swap) runs on the split-bf16 engine: it only maps a Gaussian sketch, whose rounding at
-    // 2^-24 moves the randomized SVD's result far below the split path's error
-    if (h->cfg.precision == TATRG_BF16X3) {
-      if (!gemm_bf16x3(gs, h->planes, h->planes_doubles, st, nullptr, nullptr, nullptr,
-                       h->tuned_group[2])) {
-        h->err = "split-bf16 plane workspace too small for the swap sketch map";
-        h->host_fault = true;
-      }
-    } else {
-      gemm_long_k(h, gs);
+    // (Q_B x 1)^T Omega = L2B^{-1} Q1B^T Omega: rows (p', beta).  Q1B^T Omega was formed on the
+    // side stream during the compression, unless the shifted second attempt replaced Q1B.
+    side_join_wait(h);
+    if (!h->side_ok) {
+      swap_sketch(h, st);
+      swap_sketch_map(h, Q1B, st, h->partial);
     }
+    h->side_ok = false;
     gemm(h, G(d.n2, c * w, d.n2, L2iB, d.n2, false, h->t1, c * w, false, h->P1, c * w));
     op.fa = h->cra;               // R_A
     op.na = d.n2;
@@ -921,6 +992,10 @@ bool bond_swap(tatrg_handle* h, double* rec, bool compressed) {
     gemm(h, G(d.n3, d.n2, d.n2, Q1B, d.n2, false, h->t2, d.n2, false, h->Xs, d.n2));
     perm(h, h->Xs, h->Y, {d.n3, c, c}, {1, 0, 2});
   } else {
+    // the side stream's sketch work of the compression (if any) has to end before P2 and t1
+    // are reused (a wait on an event never recorded returns at once)
+    side_join_wait(h);
+    h->side_ok = false;
     // A~ = A' S', B~ = B' S'; atf = [f', (x beta)], btx = [(x alpha), b']
     gemm(h, G(d.n4, c, c, h->A, c, false, h->Smat, c, false, h->Xs, c));
     gemm(h, G(d.n4, c, c, h->B, c, false, h->Smat, c, false, h->Ys, c));
@@ -1331,8 +1406,9 @@ bool sync_point(tatrg_handle* h, bool want_compression, bool* compressed, bool* 
                 int* verdict = nullptr) {
   *compressed = false;
   *prev_failed = false;
-  // wait for the stream, then read the verdicts (one small copy from an idle device)
+  // wait for the streams, then read the verdicts (one small copy from an idle device)
   if (hipStreamSynchronize(h->st) != hipSuccess) return false;
+  if (h->st2 && hipStreamSynchronize(h->st2) != hipSuccess) return false;
   int v[4] = {1, 0, 1, 1};
   if (hipMemcpy(v, h->vflags, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return false;
   *compressed = want_compression && v[0] == 0;
@@ -1974,6 +2050,12 @@ void tatrg_destroy(tatrg_handle* h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
   for (hipEvent_t e : h->sev) hipEventDestroy(e);
+  if (h->st2) {
+    hipStreamSynchronize(h->st2);
+    hipStreamDestroy(h->st2);
+  }
+  for (hipEvent_t e : {h->fork_ev[0], h->fork_ev[1], h->join_ev})
+    if (e) hipEventDestroy(e);
   delete h;
 }
 
