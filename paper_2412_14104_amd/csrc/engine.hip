@@ -822,6 +822,11 @@ void side_fork(tatrg_handle* h, int i) {
   hipStreamWaitEvent(h->st2, h->fork_ev[i], 0);
 }
 
+// Marks the end of the side stream's work enqueued so far (join event).
+void side_join(tatrg_handle* h) {
+  if (h->st2) hipEventRecord(h->join_ev, h->st2);
+}
+
 // Orders st after the side stream's work (no-op without a side stream or before any join).
 void side_join_wait(tatrg_handle* h) {
   if (h->st2 && h->join_ev) hipStreamWaitEvent(h->st, h->join_ev, 0);
@@ -876,7 +881,7 @@ void compress_swap_panels(tatrg_handle* h) {
   // bond swap uses it when the verdict is a compressed middle from these panels)
   side_fork(h, 1);
   swap_sketch_map(h, h->cq + n5, side, h->partial2);
-  if (h->st2) hipEventRecord(h->join_ev, h->st2);
+  side_join(h);
   h->side_ok = true;
   gemm_long_k(h, Gb(G(n2, n2, n3, h->cq, n2, true, h->cq, n2, false, h->cg2, n2), 2, n5, n5, s2));
   cholesky_blocked_inv(h->cg2, h->cdi, (int)n2, 2, h->cflag, st);
@@ -1048,18 +1053,24 @@ void isometries(tatrg_handle* h) {
   double* ly = h->Uhb + c * c;
   gemm_long_k(h, G(c, c, d.n4, h->Xs, d.n4, false, h->Xs, d.n4, true, px, c));
   gemm_long_k(h, G(c, c, d.n4, h->Ys, d.n4, false, h->Ys, d.n4, true, py, c));
-  psd_factor(px, lx, h->Shb, h->Vhb, (int)c, 2, st);
+  // the factors (a latency-bound Jacobi SVD) on the side stream while the X- and Y-type Grams,
+  // which do not need them, run here
+  const hipStream_t side = side_stream(h);
+  side_fork(h, 0);
+  psd_factor(px, lx, h->Shb, h->Vhb, (int)c, 2, side);
+  side_join(h);
   double* rA = h->rho;
   double* rX = h->rho + n2 * n2;
   double* rY = h->rho + 2 * n2 * n2;
   double* rD = h->rho + 3 * n2 * n2;
-  gemm(h, G(d.n4, c, c, h->A, c, false, lx, c, false, h->AP, c));
-  pair_gram(h, h->AP, h->AP, rA);
   // X-type: [alpha, f2, f3, f4, g] -> [(f2 f3), alpha, f4, g]
   perm(h, h->Xs, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rX, n2));
   perm(h, h->Ys, h->Ap, {c, c, c, c, c}, {1, 2, 0, 3, 4});
   gemm_long_k(h, G(n2, n2, d.n3, h->Ap, d.n3, false, h->Ap, d.n3, true, rY, n2));
+  side_join_wait(h);
+  gemm(h, G(d.n4, c, c, h->A, c, false, lx, c, false, h->AP, c));
+  pair_gram(h, h->AP, h->AP, rA);
   gemm(h, G(d.n4, c, c, h->B, c, false, ly, c, false, h->AP, c));
   pair_gram(h, h->AP, h->AP, rD);
   // the four range finders as one batched chain: U^Z lands in UZ + z n2 L
@@ -1118,22 +1129,32 @@ void squeezers(tatrg_handle* h, double* rec) {
   gemm_long_k(h, G(c, c, n4, h->Xh, c, true, h->XA, c, false, gf, c));
   gemm(h, G(c, n4, c, ddg, c, true, h->Yh, n4, false, h->XA, n4));
   gemm_long_k(h, G(c, c, n4, h->Yh, c, true, h->XA, c, false, gb, c));
-  psd_factor(gf, lf, h->Shb, h->Vhb, (int)c, 2, st);
+  const std::vector<int> a_perm[3] = {{1, 4, 0, 2, 3}, {2, 4, 0, 1, 3}, {3, 4, 0, 1, 2}};
+  const std::vector<int> x_perm[3] = {{0, 1, 2, 3, 4}, {0, 2, 1, 3, 4}, {0, 3, 1, 2, 4}};
+  const std::vector<int64_t> d5 = {c, c, c, c, c};
+  const std::vector<int64_t> d4 = {c, c, c, c};
+  // the factors (a latency-bound Jacobi SVD) on the side stream while the first Gram of Ah
+  // alone, which does not need them, runs here
+  const hipStream_t side = side_stream(h);
+  side_fork(h, 0);
+  psd_factor(gf, lf, h->Shb, h->Vhb, (int)c, 2, side);
+  side_join(h);
+  perm(h, h->Ah, h->pm1, d5, a_perm[0]);
+  gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
+  side_join_wait(h);
   // xg = Xh L_b, yg = Yh L_f: the Grams of the forward and backward pairs below are then
   // symmetric products of one operand (sum Xh g_b Xh^T = (Xh L_b)(Xh L_b)^T)
   gemm(h, G(n4, c, c, h->Xh, c, false, lb, c, false, h->xg, c));
   gemm(h, G(n4, c, c, h->Yh, c, false, lf, c, false, h->yg, c));
 
-  const std::vector<int> a_perm[3] = {{1, 4, 0, 2, 3}, {2, 4, 0, 1, 3}, {3, 4, 0, 1, 2}};
-  const std::vector<int> x_perm[3] = {{0, 1, 2, 3, 4}, {0, 2, 1, 3, 4}, {0, 3, 1, 2, 4}};
-  const std::vector<int64_t> d5 = {c, c, c, c, c};
-  const std::vector<int64_t> d4 = {c, c, c, c};
   for (int mi = 0; mi < 3; ++mi) {
     double* rl = h->rho + mi * n2 * n2;
     double* rr = h->rho + (3 + mi) * n2 * n2;
-    // rho_L = sum_{a a'} aa[u1 a u1' a'] xx[a u2 a' u2']
-    perm(h, h->Ah, h->pm1, d5, a_perm[mi]);
-    gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
+    // rho_L = sum_{a a'} aa[u1 a u1' a'] xx[a u2 a' u2'] (aa of mi = 0 is formed above)
+    if (mi > 0) {
+      perm(h, h->Ah, h->pm1, d5, a_perm[mi]);
+      gemm_long_k(h, G(n2, n2, n3, h->pm1, n3, false, h->pm1, n3, true, h->sq1, n2));
+    }
     // (x_perm[0] is the identity: xg is used as it is)
     const double* xs = h->xg;
     if (mi > 0) {
