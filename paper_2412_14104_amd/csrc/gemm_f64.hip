@@ -218,8 +218,17 @@ __global__ void splitk_reduce(const double* partial, double* C, int64_t M, int64
     const int64_t i = r / N, j = r - (r / N) * N;
     const int64_t src = (sym && i / BM > j / BN) ? j * N + i : r;
     const double* pp = partial + b * kparts * M * N + src;
+    // parts added in increasing order, eight loads in flight at a time
     double s = 0.0;
-    for (int p = 0; p < kparts; ++p) s += pp[(int64_t)p * M * N];
+    int p = 0;
+    for (; p + 8 <= kparts; p += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = pp[(int64_t)(p + t) * M * N];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s += v[t];
+    }
+    for (; p < kparts; ++p) s += pp[(int64_t)p * M * N];
     double* c = C + b * sC + i * ldc + j;
     double val = alpha * s;
     if (beta != 0.0) val += beta * *c;
@@ -240,8 +249,18 @@ __global__ __launch_bounds__(1024) void parts_reduce_kernel(const double* partia
   const int tid = threadIdx.x, ol = tid & 63, pg = tid >> 6;
   const int64_t mn = M * N, o = (int64_t)blockIdx.x * 64 + ol;
   double sum = 0.0;
-  if (o < mn)
-    for (int64_t p = pg; p < parts; p += 16) sum += partial[p * mn + o];
+  if (o < mn) {
+    // every 16th part in increasing order, eight loads in flight at a time
+    int64_t p = pg;
+    for (; p + 7 * 16 < parts; p += 8 * 16) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = partial[(p + 16 * t) * mn + o];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) sum += v[t];
+    }
+    for (; p < parts; p += 16) sum += partial[p * mn + o];
+  }
   acc[pg][ol] = sum;
   __syncthreads();
   if (pg == 0 && o < mn) {
