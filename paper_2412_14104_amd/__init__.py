@@ -101,6 +101,7 @@ _SIGS = {
     "tatrg_profile_enable": (ctypes.c_int, [_p, ctypes.c_int]),
     "tatrg_profile_read": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32), _dblp]),
     "tatrg_test_speculation": (ctypes.c_int, [_p, ctypes.c_int, ctypes.POINTER(_i64)]),
+    "tatrg_test_side_stream": (ctypes.c_int, [_p, ctypes.c_int]),
     "tatrg_profile_read_stages": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32)]),
 }
 for _name, (_res, _args) in _SIGS.items():

@@ -166,6 +166,7 @@ struct tatrg_handle {
   // work-groups), so they run beside them (fork events on st, a join event on st2).
   hipStream_t st2 = nullptr;  // created at the first step (st itself if that fails)
   bool st2_tried = false;
+  bool side_off = false;  // testing: the side work runs in order on st
   hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
   bool side_ok = false;  // t1 holds the sketch map of the current step (Q1B of the first pass)
   double* partial2 = nullptr;  // split-K partial sums of the side stream (FP64 path)
@@ -801,6 +802,7 @@ void weights_into_r(tatrg_handle* h);
 // The side stream, created at first use (default priority) with its fork and join events; the
 // handle's own stream when that fails (the side work then runs in order).
 hipStream_t side_stream(tatrg_handle* h) {
+  if (h->side_off) return h->st;
   if (!h->st2_tried) {
     h->st2_tried = true;
     if (hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking) != hipSuccess ||
@@ -817,14 +819,14 @@ hipStream_t side_stream(tatrg_handle* h) {
 
 // Orders the side stream after the work enqueued on st so far (fork event i).
 void side_fork(tatrg_handle* h, int i) {
-  if (!h->st2) return;
+  if (!h->st2 || h->side_off) return;
   hipEventRecord(h->fork_ev[i], h->st);
   hipStreamWaitEvent(h->st2, h->fork_ev[i], 0);
 }
 
 // Marks the end of the side stream's work enqueued so far (join event).
 void side_join(tatrg_handle* h) {
-  if (h->st2) hipEventRecord(h->join_ev, h->st2);
+  if (h->st2 && !h->side_off) hipEventRecord(h->join_ev, h->st2);
 }
 
 // Orders st after the side stream's work (no-op without a side stream or before any join).
@@ -2041,6 +2043,13 @@ int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
   *flops_per_launch = h->flops_per_launch;
   h->ev_used = 0;
   return 0;
+}
+
+int tatrg_test_side_stream(tatrg_handle* h, int on) {
+  if (!h) return -1;
+  const int prev = h->side_off ? 0 : 1;
+  h->side_off = on == 0;
+  return prev;
 }
 
 int tatrg_test_speculation(tatrg_handle* h, int on, int64_t* replays) {

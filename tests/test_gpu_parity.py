@@ -258,6 +258,36 @@ def test_speculative_step_replays_exactly(pkg):
     assert f == f_ref and l == l_ref, (f, f_ref)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_side_stream_run_is_bit_identical(pkg, precision):
+    """The work the step puts on the handle's side stream (the swap's sketch and its map, the
+    semidefinite factors) gives the same chi = 16 run, state and free energy bit for bit as
+    the same work run in order on the handle's own stream."""
+    import torch
+    g = golden("C2")
+    run = g["runs"][0]
+    prec = pkg.BF16X3 if precision == "split" else pkg.FP64
+    out = []
+    for on in (1, 0):
+        eng = pkg.Engine(g["chi"], g["r"], g["q"], 12, seed=g["seed"], precision=prec,
+                         record_spectra=False)
+        assert pkg.lib.tatrg_test_side_stream(eng.handle, on) == 1
+        eng.init(run["beta"])
+        for _ in range(12):
+            eng.step()
+        n5 = g["chi"] ** 5
+        phi = torch.empty(n5, dtype=torch.float64, device="cuda")
+        psi = torch.empty(n5, dtype=torch.float64, device="cuda")
+        eng.get_state(phi, psi)
+        f, l = eng.free_energy()
+        comp = [eng.swap_compressed(k) for k in range(12)]
+        out.append((f, l, phi.cpu(), psi.cpu(), comp))
+    print("compressed steps", out[0][4], flush=True)
+    assert sum(out[0][4]) > 0
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert torch.equal(out[0][2], out[1][2]) and torch.equal(out[0][3], out[1][3])
+
+
 def test_autotuned_split_run_is_bit_identical(pkg):
     """tatrg_autotune only reorders the split GEMMs' work-groups: a tuned chi = 16 split run
     gives the untuned run's free energy bit for bit, and the choices are from the table."""
