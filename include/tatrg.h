@@ -155,6 +155,17 @@ tatrg_status tatrg_free_energy(tatrg_handle* h, double* h_f, double* h_lnzv);
 tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1,
                                    double* h_d2);
 
+/* Between steps (verifies a pending step first).  The step puts work that does not depend on
+ * the latency-bound factorisations around it on a second stream of the handle (created at the
+ * first step, default priority, ordered by events): the bond swap's sketch and its map through
+ * the first orthonormal factor of the panels, Eq. (1), beside their Cholesky chains, and the
+ * semidefinite factors of the isometries and squeezers beside Grams that do not need them.
+ * on = 0 runs that work in order on the handle's own stream instead (for a process that
+ * already runs several handles at once, where the extra streams only compete for hardware
+ * queues), on != 0 restores the default.  Results are the same bit for bit either way.
+ * EINVAL for a null handle, EHIP on a HIP error. */
+tatrg_status tatrg_set_side_stream(tatrg_handle* h, int32_t on);
+
 /* Synchronising; between steps.  A measured table for the split-bf16 GEMMs of the step (the
  * contraction of Eqs. (makeMG)/(makeMH): P = E.FM4 and Phi = Qt^T.P, and the bond swap's
  * sketch map, Eq. (1)): each is timed at its real shape on the handle's scratch for

@@ -147,13 +147,6 @@ int tatrg_profile_read(struct tatrg_handle* h, double* total_ms, int32_t* launch
  * NULL) receives the number of replays so far.  Returns 0, -1 for a null handle. */
 int tatrg_test_speculation(struct tatrg_handle* h, int on, int64_t* replays);
 
-/* The handle's side stream: the swap's sketch and its map, and the semidefinite factors of the
- * isometries and squeezers, run on a second stream beside latency-bound work of the handle's
- * own stream (fork and join events).  on = 0 runs that work in order on the handle's stream
- * instead, on = 1 restores the side stream; to be called between steps.  Returns the previous
- * setting (1 = side stream), -1 for a null handle. */
-int tatrg_test_side_stream(struct tatrg_handle* h, int on);
-
 /* Stage timing of the profiled steps (tatrg_profile_enable also reserves events at the stage
  * boundaries of up to ceil(max_launches / 4) steps, on the handle's stream).  Synchronises; stage_ms[0..5] (host) receives the summed
  * device time of canonical form (S0, Section 2), bond swap (S1, Eq. (1)), isometries (S2,

@@ -61,6 +61,7 @@ _SIGS = {
     "tatrg_lognorm": (ctypes.c_int, [_p, _dblp]),
     "tatrg_free_energy": (ctypes.c_int, [_p, _dblp, _dblp]),
     "tatrg_lnz_derivatives": (ctypes.c_int, [_p, _dblp, _dblp, _dblp]),
+    "tatrg_set_side_stream": (ctypes.c_int, [_p, _i32]),
     "tatrg_autotune": (ctypes.c_int, [_p, ctypes.POINTER(_i32)]),
     "tatrg_get_spectra": (ctypes.c_int, [_p, _i32, _i32, _dblp, _i32, ctypes.POINTER(_i32)]),
     "tatrg_get_record": (ctypes.c_int, [_p, _i32, _i32, _i32, _dblp, _i32,
@@ -101,7 +102,6 @@ _SIGS = {
     "tatrg_profile_enable": (ctypes.c_int, [_p, ctypes.c_int]),
     "tatrg_profile_read": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32), _dblp]),
     "tatrg_test_speculation": (ctypes.c_int, [_p, ctypes.c_int, ctypes.POINTER(_i64)]),
-    "tatrg_test_side_stream": (ctypes.c_int, [_p, ctypes.c_int]),
     "tatrg_profile_read_stages": (ctypes.c_int, [_p, _dblp, ctypes.POINTER(_i32)]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -172,6 +172,11 @@ class Engine:
         if self.batch == 1:
             return f[0], lnzv[0]
         return list(f), list(lnzv)
+
+    def set_side_stream(self, on):
+        """Run the step's independent work on the handle's second stream (default) or, with
+        on=False, in order on its own stream; results are bit for bit the same."""
+        _check(lib.tatrg_set_side_stream(self.handle, 1 if on else 0), self.handle)
 
     def autotune(self):
         """Measured work-group grouping of the split GEMMs (tatrg_autotune): the three

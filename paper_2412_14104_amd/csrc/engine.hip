@@ -166,7 +166,7 @@ struct tatrg_handle {
   // work-groups), so they run beside them (fork events on st, a join event on st2).
   hipStream_t st2 = nullptr;  // created at the first step (st itself if that fails)
   bool st2_tried = false;
-  bool side_off = false;  // testing: the side work runs in order on st
+  bool side_off = false;  // tatrg_set_side_stream(h, 0): the side work runs in order on st
   hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
   bool side_ok = false;  // t1 holds the sketch map of the current step (Q1B of the first pass)
   double* partial2 = nullptr;  // split-K partial sums of the side stream (FP64 path)
@@ -1849,6 +1849,16 @@ tatrg_status tatrg_lnz_derivatives(tatrg_handle* h, double* h_lnzv, double* h_d1
   return s;
 }
 
+tatrg_status tatrg_set_side_stream(tatrg_handle* h, int32_t on) {
+  if (!h) return TATRG_EINVAL;
+  if (!settle(h)) {
+    h->err = "verification of the last step failed";
+    return TATRG_EHIP;
+  }
+  h->side_off = on == 0;
+  return TATRG_OK;
+}
+
 tatrg_status tatrg_autotune(tatrg_handle* h, int32_t* h_choice) {
   if (!h) return TATRG_EINVAL;
   if (h->cfg.precision != TATRG_BF16X3) {
@@ -2043,13 +2053,6 @@ int tatrg_profile_read(tatrg_handle* h, double* total_ms, int32_t* launches,
   *flops_per_launch = h->flops_per_launch;
   h->ev_used = 0;
   return 0;
-}
-
-int tatrg_test_side_stream(tatrg_handle* h, int on) {
-  if (!h) return -1;
-  const int prev = h->side_off ? 0 : 1;
-  h->side_off = on == 0;
-  return prev;
 }
 
 int tatrg_test_speculation(tatrg_handle* h, int on, int64_t* replays) {

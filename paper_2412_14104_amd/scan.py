@@ -52,6 +52,9 @@ def run_scan(betas, chi, r, q, n, seed=0, precision="fp64", engines=4, progress=
         st = torch.cuda.Stream()
         eng = Engine(chi, r, q, n, seed=seed, precision=prec, record_spectra=True,
                      batch=len(chunk), stream=st)
+        if ne > 1:
+            # the handles already fill the device: no second stream each
+            eng.set_side_stream(False)
         eng.init(chunk)
         engs.append(eng)
     torch.cuda.synchronize()

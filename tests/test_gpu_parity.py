@@ -271,7 +271,7 @@ def test_side_stream_run_is_bit_identical(pkg, precision):
     for on in (1, 0):
         eng = pkg.Engine(g["chi"], g["r"], g["q"], 12, seed=g["seed"], precision=prec,
                          record_spectra=False)
-        assert pkg.lib.tatrg_test_side_stream(eng.handle, on) == 1
+        eng.set_side_stream(on == 1)
         eng.init(run["beta"])
         for _ in range(12):
             eng.step()
