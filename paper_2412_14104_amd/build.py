@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtatrg.so")
 SOURCES = ["gemm_f64.hip", "gemm_bf16x3.hip", "linalg.hip", "misc.hip", "engine.hip", "testing.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
-         # packed fp32 instructions are disabled on the test machines
+         # packed fp32 instructions are not generated (some of their forms have given
+         # wrong results on this hardware)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-value"]
 
