@@ -21,6 +21,12 @@
  *    non-positive Cholesky pivot, non-positive final trace) set a sticky device flag that
  *    the next synchronising call reports as TATRG_ENUMERIC.  tatrg_last_error returns a
  *    message for the last failure of a handle.
+ *  - Fixed thresholds of the step (not configurable; part of what a run computes, and the
+ *    same in the independent CPU reference): singular values below 1e-11 s_max carry no
+ *    gauge; neighbouring singular values closer than 1e-6 s_max form one degenerate cluster
+ *    (at most 8 vectors), rotated to a basis fixed by 8 Philox probe vectors; squeezer modes
+ *    with S < 1e-10 S_max are masked; the squeezer Grams get 1e-13 tr(rho) added to the
+ *    diagonal before their Cholesky factorisation.
  */
 #ifndef TATRG_H
 #define TATRG_H
