@@ -184,7 +184,7 @@ struct tatrg_handle {
   double *phi, *psi, *A, *B, *X, *Y, *atf, *btx, *P1, *P2, *P3, *Gq, *t1, *t2, *tsqr_ws;
   double *Xs, *Ys, *AP, *Ap, *APp, *rho, *UZ, *E, *F, *Gt, *H;
   double *Ah, *Xh, *Yh, *Dh, *XA, *xg, *yg, *pm1, *pm3, *sq1, *sq2, *sq3, *sq4;
-  double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *q3, *Qt, *phin;
+  double *chol, *Cm, *Msq, *Nsq, *Fp, *tmp5, *FM4, *P, *q1, *q2, *Qt, *phin;
   double *partial, *probe, *small, *planes;
   // compressed cell middle of the bond swap: the two panels [f'][(x beta)], [b'][(x alpha)]
   // (cp, stride n5), their orthonormal factors (cq), the Cholesky factors of the two passes
@@ -389,7 +389,8 @@ void carve(tatrg_handle* h, Carver& cv) {
   // P in float64; on the split path the P GEMM writes P's bf16 planes here instead
   h->P = cv.take(std::max(L * L * n3, p_planes_doubles(d)));
   h->q1 = cv.take(std::max(L * n3, L * L * n2));  // [(i3a kA),(i2b k2)] then [(kA k2 k3), kX]
-  h->q2 = cv.take(L * n4); h->q3 = cv.take(L * n4);
+  // the factors of Qt and their permuted copies (3 c^3 L + c^3 + n2 L)
+  h->q2 = cv.take(3 * c * c * c * L + c * c * c + n2 * L);
   h->Qt = cv.take(L * L * n2);
   h->phin = cv.take(n5);
   h->planes_doubles = 0;
@@ -1265,11 +1266,21 @@ void contract_half(tatrg_handle* h, const double* E, const double* F, const doub
     // P[(i1 kA)][(kX g k4)] = E[(i1 kA)][(i4a a)] FM4[(i4a a)][(kX g k4)]
     gemm_timed(h, G(c * L, L * n2, n2, E, n2, false, h->FM4, L * n2, false, h->P, L * n2));
   }
-  // Qt[kA][kX][k2][k3]
+  // Qt[kA][kX][k2][k3] = sum I[(i2a i3a)][kA] S2[i2a][i2b][k2] S3[i3a][i3b][k3] J[(i2b i3b)][kX],
+  // as (I S2)(S3 J) contracted over (i3a, i2b): both factors have c^3 L entries, so no
+  // intermediate of L chi^4 entries is formed
+  double* fap = h->q2;                   // [kA][k2][i3a][i2b]
+  double* s3p = fap + c * c * c * L;     // [i3a][k3][i3b]
+  double* jp = s3p + c * c * c;          // [i3b][i2b][kX]
+  double* fb = jp + n2 * L;              // [i3a][k3][i2b][kX]
+  double* fbp = fb + c * c * c * L;      // [i3a][i2b][k3][kX]
   gemm(h, G(c * L, n2, c, I, c * L, true, S2, n2, false, h->q1, n2));        // [(i3a kA),(i2b k2)]
-  gemm(h, G(L * n2, n2, c, h->q1, L * n2, true, S3, n2, false, h->q2, n2));  // [(kA i2b k2),(i3b k3)]
-  perm(h, h->q2, h->q3, {L, c, c, c, c}, {0, 2, 4, 1, 3});                  // [kA,k2,k3,i2b,i3b]
-  gemm(h, G(L * n2, L, n2, h->q3, n2, false, J, L, false, h->q1, L));        // [(kA k2 k3), kX]
+  perm(h, h->q1, fap, {c, L, c, c}, {1, 3, 0, 2});
+  perm(h, S3, s3p, {c, c, c}, {0, 2, 1});
+  perm(h, J, jp, {c, c, L}, {1, 0, 2});
+  gemm(h, G(n2, c * L, c, s3p, c, false, jp, c * L, false, fb, c * L));     // [(i3a k3),(i2b kX)]
+  perm(h, fb, fbp, {c, c, c, L}, {0, 2, 1, 3});
+  gemm(h, G(c * L, c * L, n2, fap, n2, false, fbp, c * L, false, h->q1, c * L));  // [(kA k2),(k3 kX)]
   perm(h, h->q1, h->Qt, {L, c, c, L}, {0, 3, 1, 2});                        // [kA,kX,k2,k3]
   // phin[i1][(k2 k3)][(g k4)] = Qt^T P[i1]
   if (split) {
