@@ -164,9 +164,11 @@ void gauge_rotation(const double* s, const double* P, double* O, int n, int n_pr
 // e = i * cols + j for (seed, step, site); written to out[i*ld + j] (or out[j*ld + i] when
 // transposed).  With row_split = s > 0 (a divisor of rows), row i = u * s + v is stored as row
 // v * (rows / s) + u: a sketch whose rows are indexed (u, v) laid out in (v, u) order.
+// max_blocks > 0 caps the grid (the kernel strides over the draws), for a draw that runs
+// beside latency-bound work and should leave most of the chip to it.
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
                      uint64_t seed, uint32_t step, uint32_t site, hipStream_t st,
-                     int64_t row_split = 0);
+                     int64_t row_split = 0, int max_blocks = 0);
 
 // The generator's four 32-bit output words for counter pairs pair0 .. pair0 + npairs - 1 of
 // (seed, step, site), pair by pair (out holds 4 * npairs words, 16-byte aligned).

@@ -835,11 +835,13 @@ void side_join_wait(tatrg_handle* h) {
   if (h->st2 && h->join_ev) hipStreamWaitEvent(h->st, h->join_ev, 0);
 }
 
-// The swap's Gaussian sketch (rows (beta, b') stored in (b', beta) order) into P2, on stream st.
+// The swap's Gaussian sketch (rows (beta, b') stored in (b', beta) order) into P2, on stream st;
+// on the side stream with a grid of one work-group per CU, so that the Cholesky chain it runs
+// beside keeps its CUs.
 void swap_sketch(tatrg_handle* h, hipStream_t st) {
   const Dims& d = h->d;
   philox_gaussian(h->P2, d.n4, d.Ls, d.Ls, false, h->cfg.seed, (uint32_t)h->step, SITE_SWAP, st,
-                  d.n3);
+                  d.n3, st == h->st ? 0 : 256);
 }
 
 // The sketch mapped through the first-pass orthonormal factor of the B panel,

@@ -168,8 +168,18 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const double* __rest
     const int na = (int)(t.out_dims[t.la] - a0 < 32 ? t.out_dims[t.la] - a0 : 32);
     const int nb = (int)(t.out_dims[t.lb] - b0 < 32 ? t.out_dims[t.lb] - b0 : 32);
     __syncthreads();  // the previous tile has been written out
-    if (tx < nb)
-      for (int a = ty; a < na; a += 8) tile[a][tx] = in[in_base + (a0 + a) * sa_in + b0 + tx];
+    if (tx < nb) {
+      // the four loads of a thread are in flight together (na <= 32 = 4 x 8)
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = ty + 8 * q;
+        v[q] = (a < na) ? in[in_base + (a0 + a) * sa_in + b0 + tx] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (ty + 8 * q < na) tile[ty + 8 * q][tx] = v[q];
+    }
     __syncthreads();
     if (tx < na)
       for (int b = ty; b < nb; b += 8) out[out_base + (b0 + b) * sb_out + a0 + tx] = tile[tx][b];
@@ -342,10 +352,12 @@ __global__ __launch_bounds__(TPB) void order_param_final_kernel(const double* __
 
 void philox_gaussian(double* out, int64_t rows, int64_t cols, int64_t ld, bool transposed,
                      uint64_t seed, uint32_t step, uint32_t site, hipStream_t st,
-                     int64_t row_split) {
+                     int64_t row_split, int max_blocks) {
   const int64_t npairs = (rows * cols + 1) / 2;
   if (row_split > 0 && rows % row_split != 0) row_split = 0;  // callers pass a divisor
-  hipLaunchKernelGGL(philox_gauss_kernel, dim3(grid_for(npairs)), dim3(TPB), 0, st, out, rows,
+  unsigned blocks = grid_for(npairs);
+  if (max_blocks > 0 && blocks > (unsigned)max_blocks) blocks = (unsigned)max_blocks;
+  hipLaunchKernelGGL(philox_gauss_kernel, dim3(blocks), dim3(TPB), 0, st, out, rows,
                      cols, ld, transposed ? 1 : 0, row_split, (uint32_t)seed,
                      (uint32_t)(seed >> 32), step, site);
 }
