@@ -15,7 +15,9 @@
  *  - Matrices are row-major float64.  The caller owns every buffer passed in, including the
  *    workspace; the library never allocates device memory after tatrg_create returns.
  *  - Calls are asynchronous on the stream given to tatrg_create unless documented as
- *    synchronising.  A handle must not be used from two threads at once.
+ *    synchronising (a step also runs work on a second stream of the handle, ordered by
+ *    events, so that all of it is complete wherever the caller's stream is; see
+ *    tatrg_set_side_stream).  A handle must not be used from two threads at once.
  *  - Errors: invalid arguments are reported synchronously (TATRG_EINVAL); HIP launch
  *    errors as TATRG_EHIP; numerical faults detected on the device (non-finite c_k,
  *    non-positive Cholesky pivot, non-positive final trace) set a sticky device flag that
