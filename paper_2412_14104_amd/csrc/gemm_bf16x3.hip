@@ -330,35 +330,51 @@ int64_t plane_batches(const GemmArgs& g, bool a_side) {
 // The planes of the contraction's FM4 operand straight from tmp[(i4a k4)][(a kX g)] (leg
 // extents c, c, c, L, c): plane row n = (g, k4, kX), column k = (i4a, a), i.e. FM4 with kX
 // innermost, transposed to the k-contiguous layout the split GEMM reads, without storing FM4
-// in float64.  One 32 x 32 tile of (a, g) per work-group for one (i4a, k4, kX), transposed
-// through LDS; every value is split exactly as split3_kernel splits it.
+// in float64.  One work-group per (k4, kX), group of FM4_I consecutive i4a and 32 x 32 tile of
+// (a, g), transposed through LDS: the reads run along g, and each plane row takes FM4_I
+// consecutive runs of a, contiguous when the a tile is whole.  Every value is split exactly as
+// split3_kernel splits it.
+constexpr int FM4_I = 4;
+
 __global__ __launch_bounds__(256) void fm4_planes_kernel(const double* __restrict__ tmp, int c,
                                                          int L, int64_t Kp,
                                                          uint16_t* __restrict__ p0,
                                                          uint16_t* __restrict__ p1,
                                                          uint16_t* __restrict__ p2) {
-  __shared__ double tile[32][33];  // [a][g]
+  __shared__ double tile[FM4_I][32][33];  // [i4a - i0][a][g]
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;   // (i4a, k4, kX)
+  const int64_t blk = blockIdx.x;  // (i4a group, k4, kX)
   const int kX = (int)(blk % L);
   const int k4 = (int)((blk / L) % c);
-  const int i4a = (int)(blk / ((int64_t)L * c));
+  const int i0 = FM4_I * (int)(blk / ((int64_t)L * c));
   const int a0 = 32 * (int)blockIdx.y, g0 = 32 * (int)blockIdx.z;
-  // tmp row (i4a k4), column (a kX g): contiguous in g
-  const double* src = tmp + ((int64_t)i4a * c + k4) * ((int64_t)c * L * c);
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
-    const int aa = idx / 32, gg = idx % 32;
-    const int a = a0 + aa, g = g0 + gg;
-    tile[aa][gg] = (a < c && g < c) ? src[((int64_t)a * L + kX) * c + g] : 0.0;
+  // tmp row (i4a k4), column (a kX g): contiguous in g; all of a thread's loads in flight
+  // before the LDS writes
+  double v[FM4_I * 32 * 32 / 256];
+#pragma unroll
+  for (int q = 0; q < FM4_I * 4; ++q) {
+    const int idx = tid + 256 * q, ii = idx / 1024, aa = (idx / 32) % 32, gg = idx % 32;
+    const int i4a = i0 + ii, a = a0 + aa, g = g0 + gg;
+    v[q] = (i4a < c && a < c && g < c)
+               ? tmp[(((int64_t)i4a * c + k4) * c + a) * ((int64_t)L * c) + (int64_t)kX * c + g]
+               : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < FM4_I * 4; ++q) {
+    const int idx = tid + 256 * q;
+    tile[idx / 1024][(idx / 32) % 32][idx % 32] = v[q];
   }
   __syncthreads();
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
-    const int gg = idx / 32, aa = idx % 32;
-    const int a = a0 + aa, g = g0 + gg;
-    if (a < c && g < c) {
-      const double v = tile[aa][gg];
-      const uint16_t h0 = bf16_rne((float)v);
-      const double r1 = v - bf16_to_double(h0);
+  // plane row (g k4 kX), columns i4a c + a: consecutive threads take consecutive a, then i4a
+#pragma unroll 4
+  for (int q = 0; q < FM4_I * 4; ++q) {
+    const int idx = tid + 256 * q, gg = idx / (32 * FM4_I), ii = (idx / 32) % FM4_I,
+              aa = idx % 32;
+    const int i4a = i0 + ii, a = a0 + aa, g = g0 + gg;
+    if (i4a < c && a < c && g < c) {
+      const double x = tile[ii][aa][gg];
+      const uint16_t h0 = bf16_rne((float)x);
+      const double r1 = x - bf16_to_double(h0);
       const uint16_t h1 = bf16_rne((float)r1);
       const double r2 = r1 - bf16_to_double(h1);
       const int64_t row = ((int64_t)g * c + k4) * L + kX;
@@ -395,7 +411,8 @@ bool fm4_planes(const double* tmp, int c, int L, uint16_t* planes, int64_t cap,
     hipLaunchKernelGGL(zero_plane_tail_kernel, grid, dim3(256), 0, st, p0, p1, p2, rows, n2, Kp,
                        (int64_t)0);
   }
-  dim3 grid((unsigned)((int64_t)c * c * L), (unsigned)((c + 31) / 32), (unsigned)((c + 31) / 32));
+  dim3 grid((unsigned)((int64_t)((c + FM4_I - 1) / FM4_I) * c * L), (unsigned)((c + 31) / 32),
+            (unsigned)((c + 31) / 32));
   hipLaunchKernelGGL(fm4_planes_kernel, grid, dim3(256), 0, st, tmp, c, L, Kp, p0, p1, p2);
   return true;
 }
