@@ -67,6 +67,10 @@ def test_short_workspace_and_call_order(pkg):
     f = ctypes.c_double()
     assert pkg.lib.tatrg_free_energy(h, ctypes.byref(f), None) == -5
     assert b"beta" in pkg.lib.tatrg_last_error(h) or True
+    # the side-stream switch is host state (no step pending): OK on a handle, EINVAL on none
+    assert pkg.lib.tatrg_set_side_stream(h, 0) == 0
+    assert pkg.lib.tatrg_set_side_stream(h, 1) == 0
+    assert pkg.lib.tatrg_set_side_stream(None, 1) == -1
     pkg.lib.tatrg_destroy(h)
 
 
