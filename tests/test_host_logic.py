@@ -80,3 +80,29 @@ def test_presets_data_matches_the_workloads():
                              "betas": [0.1496947]}
     betas = PRESETS["C4"]["betas"]
     assert betas == [0.140 + 0.020 * i / 63 for i in range(64)]
+
+
+def test_qt_contraction_orders_agree():
+    """The step forms Qt[kA][kX][k2][k3] = sum I[(i2a i3a)][kA] S2[i2a][i2b][k2]
+    S3[i3a][i3b][k3] J[(i2b i3b)][kX] as (I S2)(S3 J) contracted over (i3a, i2b), with the
+    leg orders of its GEMMs; this checks those index orders against the defining sum (small
+    chi and L, numpy)."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    c, L = 3, 4
+    n2 = c * c
+    I = rng.standard_normal((n2, L))
+    J = rng.standard_normal((n2, L))
+    S2 = rng.standard_normal((c, c, c))
+    S3 = rng.standard_normal((c, c, c))
+    ref = np.einsum("pqA,pbk,qel,beX->AXkl", I.reshape(c, c, L), S2, S3, J.reshape(c, c, L))
+    # q1[(i3a kA),(i2b k2)] = I^T S2 over i2a, as the first GEMM (A viewed [i2a][(i3a kA)])
+    q1 = I.reshape(c, c * L).T @ S2.reshape(c, c * c)
+    fap = q1.reshape(c, L, c, c).transpose(1, 3, 0, 2).reshape(L * c, c * c)  # [kA k2][i3a i2b]
+    s3p = S3.transpose(0, 2, 1).reshape(c * c, c)                             # [i3a k3][i3b]
+    jp = J.reshape(c, c, L).transpose(1, 0, 2).reshape(c, c * L)              # [i3b][i2b kX]
+    fb = s3p @ jp                                                             # [i3a k3][i2b kX]
+    fbp = fb.reshape(c, c, c, L).transpose(0, 2, 1, 3).reshape(c * c, c * L)  # [i3a i2b][k3 kX]
+    out = fap @ fbp                                                           # [kA k2][k3 kX]
+    qt = out.reshape(L, c, c, L).transpose(0, 3, 1, 2)                        # [kA kX k2 k3]
+    assert np.allclose(qt, ref, rtol=1e-13, atol=1e-13)
